@@ -1,0 +1,150 @@
+/*
+ * fcm.h -- C ABI of the gfx950 Fuzzy C-Means segmentation library.
+ *
+ * The library clusters 8-bit images or volumes by grey level with Fuzzy
+ * C-Means (FCM): objective J_m = sum_i sum_j u_ij^m (x_i - v_j)^2 (Eq.1) under
+ * sum_j u_ij = 1 (Eq.2), alternating the centroid update
+ * v_j = sum_i u_ij^m x_i / sum_i u_ij^m (Eq.3) and the membership update
+ * u_ij = 1 / sum_k (d_ij / d_ik)^(2/(m-1)) (Eq.4) until the largest change of
+ * any membership between two iterations falls below eps (Algorithm 1), then
+ * assigning each voxel to its cluster of largest membership (defuzzification,
+ * Sec. 2.1 and Sec. 4.3).  The problem statement -- pixel array in, cluster
+ * count c, fuzziness m and eps as parameters, cluster centres and the
+ * segmented image out -- is that of Algorithm 1 and Sec. 4.1-4.3.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HIP device memory); all other
+ *     pointers are host pointers.  Device buffers passed in are borrowed: the
+ *     caller owns them and keeps them valid while the handle uses them.
+ *   - All GPU work is enqueued on the stream given to fcm_init (a hipStream_t
+ *     passed as void*; NULL means the null stream).  Only fcm_iterate,
+ *     fcm_solve, fcm_centroids and fcm_trajectory wait for that stream.
+ *   - Functions return an int status: FCM_OK (0), FCM_NOT_CONVERGED (1),
+ *     FCM_RUNNING (2), or a negative error.  Arguments are validated before any
+ *     HIP call; on error nothing is enqueued and outputs are left untouched.
+ *     No C++ exception crosses this boundary.
+ *   - A handle is not re-entrant; distinct handles may be used concurrently on
+ *     distinct streams.
+ */
+#ifndef FCM_H
+#define FCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FCM_OK              0   /* converged: max |dU| < eps at iteration T */
+#define FCM_NOT_CONVERGED   1   /* max_iter iterations ran; result is v^max_iter */
+#define FCM_RUNNING         2   /* neither converged nor out of iterations yet */
+#define FCM_EINVAL        (-1)  /* invalid argument */
+#define FCM_ENOMEM        (-2)  /* device or host allocation failed */
+#define FCM_EDEVICE       (-3)  /* a HIP call failed (message: fcm_last_error) */
+#define FCM_ESTATE        (-4)  /* call out of order (e.g. labels before init) */
+#define FCM_ENUMERIC      (-5)  /* a non-finite centroid or objective appeared */
+#define FCM_EUNSUPPORTED  (-6)  /* configuration not built into this library */
+
+#define FCM_MAX_CLUSTERS 8
+
+/* initialisation of the centroids v^0 */
+#define FCM_INIT_LINSPACE 0     /* v_j = lo + j (hi - lo) / (C - 1) over the data range,
+                                   evaluated in FP64, rounded to FP32 */
+#define FCM_INIT_GIVEN    1     /* v^0 = init_centroids, rounded to FP32 */
+
+/* flags */
+#define FCM_F_KAHAN_ONLY  (1u << 0)  /* cross-block reduction in compensated FP32
+                                        instead of FP64 */
+#define FCM_F_TIMING      (1u << 1)  /* time every fused pass with HIP events */
+
+/* iteration drivers */
+#define FCM_DRIVER_LOOP   0     /* one launch per pass from the host */
+#define FCM_DRIVER_GRAPH  1     /* a hipGraph of graph_k passes, replayed */
+
+typedef struct fcm_params {
+    int32_t n_clusters;           /* C, 2..FCM_MAX_CLUSTERS */
+    double  m;                    /* fuzziness, finite and > 1 */
+    double  eps;                  /* stop when max_ij |u_ij^t - u_ij^(t-1)| < eps; finite, > 0 */
+    int32_t max_iter;             /* >= 1 */
+    int32_t init;                 /* FCM_INIT_* */
+    const double* init_centroids; /* host, C finite values, read only with FCM_INIT_GIVEN */
+    uint32_t flags;               /* FCM_F_* */
+} fcm_params;
+
+typedef struct fcm_tuning {
+    int32_t block;      /* threads per block of the fused pass: 256 (the only size built) */
+    int32_t grid;       /* blocks of the fused pass; 0 picks from the device and n */
+    int32_t unroll;     /* 16-voxel chunks in flight per thread: 1 or 2 */
+    int32_t driver;     /* FCM_DRIVER_* */
+    int32_t graph_k;    /* passes per host synchronisation (and per graph), 1..64 */
+} fcm_tuning;
+
+typedef struct fcm_result {
+    int32_t iters;      /* T: iterations completed (0 after the first pass) */
+    int32_t passes;     /* fused passes executed (T + 1 once finished) */
+    int32_t status;     /* FCM_OK, FCM_NOT_CONVERGED, FCM_RUNNING or FCM_ENUMERIC */
+    int32_t n_clusters;
+    double  delta;      /* max |dU| of iteration T (NaN for T = 0) */
+    double  J;          /* J_m(U^T, v^T) */
+    double  centroids[FCM_MAX_CLUSTERS]; /* v^T, the centroids that produced U^T */
+    double  kernel_ms;  /* with FCM_F_TIMING: summed event time of the passes run */
+    int32_t lo, hi;     /* smallest and largest grey level of the data */
+} fcm_result;
+
+typedef struct fcm_handle fcm_handle;
+
+/* Create a solver for d_x[0..n) (uint8 grey levels, any alignment, borrowed,
+ * never written).  Validates, allocates the handle's workspace (O(grid * C)
+ * partial sums plus O(max_iter * C) history), and enqueues the data-range pass
+ * that computes lo, hi and v^0.  n >= 1; n < C is allowed.
+ * Errors: FCM_EINVAL (null pointers, n < 1, C outside 2..8, m <= 1 or not
+ * finite, eps <= 0 or not finite, max_iter < 1, bad init mode, non-finite
+ * given centroids, unknown flags), FCM_ENOMEM, FCM_EDEVICE. */
+int fcm_init(fcm_handle** h, const uint8_t* d_x, int64_t n, const fcm_params* p, void* stream);
+
+/* Restart the solve from v^0 on the same input: enqueues the data-range pass
+ * again (the input may have new contents of the same size) and clears the
+ * iteration history and the FCM_F_TIMING total.  No allocation. */
+int fcm_reset(fcm_handle* h);
+
+/* Override the launch configuration (before the first pass, or between
+ * calls).  FCM_EINVAL for values outside the documented ranges. */
+int fcm_set_tuning(fcm_handle* h, const fcm_tuning* t);
+int fcm_get_tuning(const fcm_handle* h, fcm_tuning* t);
+
+/* Run up to k more fused passes (stopping early once finished), wait for the
+ * stream, and report the state.  Returns the result status (FCM_RUNNING if
+ * more iterations remain) or a negative error. */
+int fcm_iterate(fcm_handle* h, int32_t k, fcm_result* out);
+
+/* Iterate to convergence or max_iter and report (Algorithm 1). */
+int fcm_solve(fcm_handle* h, fcm_result* out);
+
+/* Defuzzify (Sec. 2.1, Sec. 4.3): d_labels[i] = argmin_j |x_i - v_j^T| in FP64,
+ * ties to the lowest j, which is the cluster of largest membership for m > 1.
+ * d_labels: caller-owned device buffer of n bytes.  Enqueued, not waited for. */
+int fcm_labels(fcm_handle* h, uint8_t* d_labels);
+
+/* Copy v^T (C doubles) to the host buffer out. */
+int fcm_centroids(fcm_handle* h, double* out);
+
+/* Iteration history: v^t (C doubles into v_out, may be NULL), delta^t and J^t
+ * (may be NULL) for 0 <= t <= T.  FCM_EINVAL for t outside that range. */
+int fcm_trajectory(fcm_handle* h, int32_t t, double* v_out, double* delta, double* J);
+
+/* Release the handle's workspace (waits for the stream).  NULL is ignored. */
+void fcm_destroy(fcm_handle* h);
+
+/* Static description of a status code, and the last HIP error text of this thread. */
+const char* fcm_strerror(int status);
+const char* fcm_last_error(void);
+
+/* Library version, as major * 10000 + minor * 100 + patch. */
+int fcm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCM_H */

@@ -1,0 +1,8 @@
+"""gfx950 Fuzzy C-Means segmentation (arXiv 1601.00072), Python binding of libfcm.so.
+
+PyTorch supplies device memory and streams; every step of the iteration runs
+in the library's HIP kernels.
+"""
+from .api import FCM, FcmError, Result, solve
+
+__all__ = ["FCM", "FcmError", "Result", "solve"]

@@ -1,0 +1,120 @@
+"""ctypes declarations of include/fcm.h and the loader of the in-tree libfcm.so.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  There is no fallback -- if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfcm.so")
+
+FCM_OK = 0
+FCM_NOT_CONVERGED = 1
+FCM_RUNNING = 2
+FCM_EINVAL = -1
+FCM_ENOMEM = -2
+FCM_EDEVICE = -3
+FCM_ESTATE = -4
+FCM_ENUMERIC = -5
+FCM_EUNSUPPORTED = -6
+
+FCM_MAX_CLUSTERS = 8
+FCM_INIT_LINSPACE = 0
+FCM_INIT_GIVEN = 1
+FCM_F_KAHAN_ONLY = 1 << 0
+FCM_F_TIMING = 1 << 1
+FCM_DRIVER_LOOP = 0
+FCM_DRIVER_GRAPH = 1
+
+# every symbol include/fcm.h declares
+EXPORTS = (
+    "fcm_init", "fcm_reset", "fcm_set_tuning", "fcm_get_tuning", "fcm_iterate", "fcm_solve", "fcm_labels",
+    "fcm_centroids", "fcm_trajectory", "fcm_destroy", "fcm_strerror", "fcm_last_error", "fcm_version",
+)
+
+
+class FcmParams(ctypes.Structure):
+    _fields_ = [
+        ("n_clusters", ctypes.c_int32),
+        ("m", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("init", ctypes.c_int32),
+        ("init_centroids", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class FcmTuning(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
+        ("driver", ctypes.c_int32),
+        ("graph_k", ctypes.c_int32),
+    ]
+
+
+class FcmResult(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("passes", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("n_clusters", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("centroids", ctypes.c_double * FCM_MAX_CLUSTERS),
+        ("kernel_ms", ctypes.c_double),
+        ("lo", ctypes.c_int32),
+        ("hi", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libfcm.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1601_00072_amd.build`")
+    try:
+        import torch  # noqa: F401  (brings in the HIP runtime the tensors live in)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.fcm_init.argtypes = [ctypes.POINTER(vp), vp, i64, ctypes.POINTER(FcmParams), vp]
+    lib.fcm_init.restype = ctypes.c_int
+    lib.fcm_reset.argtypes = [vp]
+    lib.fcm_reset.restype = ctypes.c_int
+    lib.fcm_set_tuning.argtypes = [vp, ctypes.POINTER(FcmTuning)]
+    lib.fcm_set_tuning.restype = ctypes.c_int
+    lib.fcm_get_tuning.argtypes = [vp, ctypes.POINTER(FcmTuning)]
+    lib.fcm_get_tuning.restype = ctypes.c_int
+    lib.fcm_iterate.argtypes = [vp, i32, ctypes.POINTER(FcmResult)]
+    lib.fcm_iterate.restype = ctypes.c_int
+    lib.fcm_solve.argtypes = [vp, ctypes.POINTER(FcmResult)]
+    lib.fcm_solve.restype = ctypes.c_int
+    lib.fcm_labels.argtypes = [vp, vp]
+    lib.fcm_labels.restype = ctypes.c_int
+    lib.fcm_centroids.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.fcm_centroids.restype = ctypes.c_int
+    lib.fcm_trajectory.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.fcm_trajectory.restype = ctypes.c_int
+    lib.fcm_destroy.argtypes = [vp]
+    lib.fcm_destroy.restype = None
+    lib.fcm_strerror.argtypes = [ctypes.c_int]
+    lib.fcm_strerror.restype = ctypes.c_char_p
+    lib.fcm_last_error.argtypes = []
+    lib.fcm_last_error.restype = ctypes.c_char_p
+    lib.fcm_version.argtypes = []
+    lib.fcm_version.restype = ctypes.c_int
+    _lib = lib
+    return lib

@@ -1,0 +1,176 @@
+"""Python face of the C ABI: one ``FCM`` object per solver handle."""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+
+from . import _lib as L
+
+
+class FcmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        lib = L.load()
+        msg = lib.fcm_strerror(status).decode()
+        detail = lib.fcm_last_error().decode() if status == L.FCM_EDEVICE else ""
+        super().__init__(f"{what}: {msg} ({status}){' -- ' + detail if detail else ''}")
+        self.status = status
+
+
+@dataclasses.dataclass
+class Result:
+    iters: int
+    passes: int
+    status: int
+    delta: float
+    J: float
+    centroids: np.ndarray
+    kernel_ms: float
+    lo: int
+    hi: int
+
+    @property
+    def converged(self) -> bool:
+        return self.status == L.FCM_OK
+
+
+def _result(r: L.FcmResult) -> Result:
+    C = r.n_clusters
+    return Result(iters=r.iters, passes=r.passes, status=r.status, delta=r.delta, J=r.J,
+                  centroids=np.array(r.centroids[:C], dtype=np.float64), kernel_ms=r.kernel_ms,
+                  lo=r.lo, hi=r.hi)
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class FCM:
+    """Fuzzy C-Means solver over a uint8 device tensor (any shape, contiguous).
+
+    ``init`` is None (evenly spaced over the data range) or a sequence of C
+    starting centroids.  The tensor is borrowed: keep it alive and unmodified
+    while the solver exists."""
+
+    def __init__(self, x, n_clusters: int, m: float = 2.0, eps: float = 1e-5, max_iter: int = 300,
+                 init=None, kahan_only: bool = False, timing: bool = False, stream=None):
+        import torch
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.uint8 or not x.is_cuda:
+            raise TypeError("x must be a uint8 CUDA/HIP tensor")
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        self._lib = L.load()
+        self.x = x
+        self.n = x.numel()
+        self.C = int(n_clusters)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(x.device)
+        flags = (L.FCM_F_KAHAN_ONLY if kahan_only else 0) | (L.FCM_F_TIMING if timing else 0)
+        self._init_buf = None
+        if init is None:
+            mode, ptr = L.FCM_INIT_LINSPACE, None
+        else:
+            v = np.ascontiguousarray(np.asarray(init, dtype=np.float64))
+            if v.shape != (self.C,):
+                raise ValueError("init must hold n_clusters values")
+            self._init_buf = (ctypes.c_double * self.C)(*v.tolist())
+            mode, ptr = L.FCM_INIT_GIVEN, ctypes.cast(self._init_buf, ctypes.POINTER(ctypes.c_double))
+        p = L.FcmParams(n_clusters=self.C, m=float(m), eps=float(eps), max_iter=int(max_iter), init=mode,
+                        init_centroids=ptr, flags=flags)
+        self._h = ctypes.c_void_p()
+        rc = self._lib.fcm_init(ctypes.byref(self._h), ctypes.c_void_p(x.data_ptr()), self.n, ctypes.byref(p),
+                                ctypes.c_void_p(self._stream.cuda_stream))
+        if rc != L.FCM_OK:
+            self._h = None
+            raise FcmError(rc, "fcm_init")
+
+    # -- tuning ---------------------------------------------------------------
+    @property
+    def tuning(self) -> dict:
+        t = L.FcmTuning()
+        self._check(self._lib.fcm_get_tuning(self._h, ctypes.byref(t)), "fcm_get_tuning")
+        return {f: getattr(t, f) for f, _ in L.FcmTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning
+        cur.update(kw)
+        if "grid" not in kw:
+            cur["grid"] = 0
+        t = L.FcmTuning(**cur)
+        self._check(self._lib.fcm_set_tuning(self._h, ctypes.byref(t)), "fcm_set_tuning")
+
+    # -- iteration --------------------------------------------------------------
+    def reset(self):
+        """Restart from v^0 on the same (possibly rewritten) input; no allocation."""
+        self._check(self._lib.fcm_reset(self._h), "fcm_reset")
+
+    def iterate(self, k: int) -> Result:
+        r = L.FcmResult()
+        rc = self._lib.fcm_iterate(self._h, int(k), ctypes.byref(r))
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_iterate")
+        return _result(r)
+
+    def solve(self) -> Result:
+        r = L.FcmResult()
+        rc = self._lib.fcm_solve(self._h, ctypes.byref(r))
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_solve")
+        return _result(r)
+
+    def labels(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(self.x)
+        if out.dtype != torch.uint8 or not out.is_cuda or out.numel() != self.n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 device tensor of the input's size")
+        self._check(self._lib.fcm_labels(self._h, ctypes.c_void_p(out.data_ptr())), "fcm_labels")
+        return out
+
+    def centroids(self) -> np.ndarray:
+        buf = (ctypes.c_double * self.C)()
+        self._check(self._lib.fcm_centroids(self._h, buf), "fcm_centroids")
+        return np.array(buf[:], dtype=np.float64)
+
+    def trajectory(self, t: int):
+        v = (ctypes.c_double * self.C)()
+        d, J = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.fcm_trajectory(self._h, int(t), v, ctypes.byref(d), ctypes.byref(J)),
+                    "fcm_trajectory")
+        return np.array(v[:], dtype=np.float64), d.value, J.value
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fcm_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if self._h is None:
+            raise FcmError(L.FCM_ESTATE, what)
+        if rc != L.FCM_OK:
+            raise FcmError(rc, what)
+
+
+def solve(x, n_clusters: int, m: float = 2.0, eps: float = 1e-5, max_iter: int = 300, init=None,
+          kahan_only: bool = False, labels: bool = True):
+    """One-shot solve: returns (Result, labels tensor or None)."""
+    with FCM(x, n_clusters, m=m, eps=eps, max_iter=max_iter, init=init, kahan_only=kahan_only) as f:
+        res = f.solve()
+        lab = f.labels() if labels else None
+        return res, lab

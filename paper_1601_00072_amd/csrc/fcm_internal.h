@@ -1,0 +1,82 @@
+// Internal layout shared by the gfx950 kernels and the host runtime (not part of the ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace fcm {
+
+constexpr int kMaxC = 8;
+constexpr int kBlock = 256;          // threads per block of every streaming kernel
+constexpr int kMaxGrid = 8192;       // capacity of the partial-sum table
+
+// Device-resident solver state.  Written only by the last block of a pass (or
+// of the data-range pass); read by every block at the start of the next one.
+struct DevState {
+    int32_t pass;        // index p of the next fused pass (pass p computes U^p)
+    int32_t done;        // nonzero once converged, out of iterations, or non-finite
+    int32_t iters;       // last completed iteration t (-1 before the first pass)
+    int32_t status;      // FCM_* status of the solve
+    uint32_t ticket;     // arrival counter of the running pass; 0 between passes
+    int32_t passes;      // fused passes executed
+    int32_t lo, hi;      // grey-level range of the data
+    double delta;        // max |dU| of iteration `iters` (NaN for iteration 0)
+    double J;            // J_m(U^iters, v^iters)
+    double vres[kMaxC];  // v^iters in FP64: the current result
+    float v32[2][kMaxC]; // FP32 centroids used by the passes: v32[p & 1] = fl32(v^p)
+};
+
+// Per-block partial row of a fused pass, stored column-major in a
+// [rows][grid] float table so that the final reduction reads it coalesced.
+// Rows: for each k < C: num (sum, comp), den (sum, comp); then J (sum, comp);
+// then delta (max).  Row count 4C + 3.
+__host__ __device__ constexpr int partial_rows(int C) { return 4 * C + 3; }
+
+enum MClass : int { kM2 = 0, kMGeneric = 1 };
+
+struct PassArgs {
+    const uint8_t* x;      // voxel grey levels
+    int64_t n;             // voxel count
+    int64_t head;          // voxels before the first 16-byte aligned address
+    int64_t nbody;         // 16-voxel chunks of the aligned body
+    DevState* st;
+    float* partials;       // [partial_rows(C)][grid]
+    double* hist_v;        // [(max_iter + 2) * C]
+    double* hist_d;        // [max_iter + 2]
+    double* hist_J;        // [max_iter + 2]
+    double eps;
+    float alpha;           // 1 / (m - 1)
+    float mexp;            // m
+    int32_t max_iter;
+    int32_t kahan_only;    // cross-block reduction in compensated FP32
+};
+
+struct InitArgs {
+    const uint8_t* x;
+    int64_t n, head, nbody;
+    DevState* st;
+    uint32_t* partials;    // [2][grid]
+    double* hist_v;
+    int32_t C;
+    int32_t given;         // 1: use v0 below, else evenly spaced over [lo, hi]
+    double v0[kMaxC];
+};
+
+struct LabelArgs {
+    const uint8_t* x;
+    uint8_t* labels;
+    int64_t n, head, nbody;
+    const DevState* st;
+    const double* hist_v;
+    int32_t C;
+    int32_t bytewise;      // x and labels differ in 16-byte alignment
+};
+
+// Launchers (fcm_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass(const PassArgs& a, int C, int mclass, int unroll, int grid, hipStream_t s);
+hipError_t launch_labels(const LabelArgs& a, int grid, hipStream_t s);
+bool pass_supported(int C, int mclass, int unroll);
+
+}  // namespace fcm

@@ -1,0 +1,103 @@
+"""The C-ABI library on the host: it loads, exports what include/fcm.h declares,
+and rejects invalid arguments before any HIP call (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1601_00072_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1601_00072_amd import build
+        build.build()
+    return L.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(fcm_\w+)\s*\(", text))
+
+
+def test_header_matches_binding_table():
+    assert declared_functions() == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (fcm_\w+)", out))
+    assert declared_functions() <= exported
+    for name in declared_functions():
+        assert getattr(lib, name) is not None
+
+
+def test_version_and_strerror(lib):
+    assert lib.fcm_version() == 10000
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        assert lib.fcm_strerror(code)
+    assert lib.fcm_strerror(12345) == b"unknown status"
+
+
+def _params(**kw):
+    d = dict(n_clusters=4, m=2.0, eps=1e-5, max_iter=300, init=L.FCM_INIT_LINSPACE,
+             init_centroids=None, flags=0)
+    d.update(kw)
+    return L.FcmParams(**d)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_clusters=1), dict(n_clusters=9), dict(n_clusters=-3),
+    dict(m=1.0), dict(m=0.5), dict(m=math.nan), dict(m=math.inf),
+    dict(eps=0.0), dict(eps=-1.0), dict(eps=math.nan), dict(eps=math.inf),
+    dict(max_iter=0), dict(max_iter=-5),
+    dict(init=7), dict(init=L.FCM_INIT_GIVEN),
+    dict(flags=1 << 9),
+])
+def test_init_rejects_invalid_params(lib, kw):
+    h = ctypes.c_void_p()
+    p = _params(**kw)
+    assert lib.fcm_init(ctypes.byref(h), FAKE, 100, ctypes.byref(p), None) == L.FCM_EINVAL
+    assert not h.value
+
+
+def test_init_rejects_nonfinite_given_centroids(lib):
+    buf = (ctypes.c_double * 4)(1.0, math.nan, 3.0, 4.0)
+    p = _params(init=L.FCM_INIT_GIVEN, init_centroids=ctypes.cast(buf, ctypes.POINTER(ctypes.c_double)))
+    h = ctypes.c_void_p()
+    assert lib.fcm_init(ctypes.byref(h), FAKE, 100, ctypes.byref(p), None) == L.FCM_EINVAL
+
+
+def test_init_rejects_bad_pointers_and_sizes(lib):
+    h = ctypes.c_void_p()
+    p = _params()
+    assert lib.fcm_init(ctypes.byref(h), None, 100, ctypes.byref(p), None) == L.FCM_EINVAL
+    assert lib.fcm_init(ctypes.byref(h), FAKE, 0, ctypes.byref(p), None) == L.FCM_EINVAL
+    assert lib.fcm_init(ctypes.byref(h), FAKE, -4, ctypes.byref(p), None) == L.FCM_EINVAL
+    assert lib.fcm_init(None, FAKE, 100, ctypes.byref(p), None) == L.FCM_EINVAL
+    assert lib.fcm_init(ctypes.byref(h), FAKE, 100, None, None) == L.FCM_EINVAL
+
+
+def test_null_handle_calls(lib):
+    r = L.FcmResult()
+    t = L.FcmTuning(block=256, grid=0, unroll=1, driver=1, graph_k=8)
+    buf = (ctypes.c_double * 8)()
+    assert lib.fcm_iterate(None, 1, ctypes.byref(r)) == L.FCM_EINVAL
+    assert lib.fcm_solve(None, ctypes.byref(r)) == L.FCM_EINVAL
+    assert lib.fcm_labels(None, FAKE) == L.FCM_EINVAL
+    assert lib.fcm_centroids(None, buf) == L.FCM_EINVAL
+    assert lib.fcm_trajectory(None, 0, buf, None, None) == L.FCM_EINVAL
+    assert lib.fcm_set_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
+    assert lib.fcm_get_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
+    lib.fcm_destroy(None)
