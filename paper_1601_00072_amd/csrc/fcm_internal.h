@@ -33,7 +33,7 @@ struct DevState {
 // then delta (max).  Row count 4C + 3.
 __host__ __device__ constexpr int partial_rows(int C) { return 4 * C + 3; }
 
-enum MClass : int { kM2 = 0, kMGeneric = 1 };
+enum MClass : int { kM2 = 0, kM15 = 1, kMGeneric = 2 };
 
 struct PassArgs {
     const uint8_t* x;      // voxel grey levels

