@@ -61,6 +61,14 @@ extern "C" {
 /* iteration drivers */
 #define FCM_DRIVER_LOOP   0     /* one launch per pass from the host */
 #define FCM_DRIVER_GRAPH  1     /* a hipGraph of graph_k passes, replayed */
+#define FCM_DRIVER_PERSISTENT 2 /* one cooperative launch runs the data-range pass
+                                   and every pass of a solve (default where
+                                   supported) */
+
+/* how the blocks of a persistent launch combine their partial sums each pass */
+#define FCM_EXCHANGE_AUTO      0  /* all-gather on small grids, else leader */
+#define FCM_EXCHANGE_LEADER    1  /* block 0 reduces and broadcasts the decision */
+#define FCM_EXCHANGE_ALLGATHER 2  /* every block reduces every partial row itself */
 
 typedef struct fcm_params {
     int32_t n_clusters;           /* C, 2..FCM_MAX_CLUSTERS */
@@ -74,10 +82,14 @@ typedef struct fcm_params {
 
 typedef struct fcm_tuning {
     int32_t block;      /* threads per block of the fused pass: 256 (the only size built) */
-    int32_t grid;       /* blocks of the fused pass; 0 picks from the device and n */
+    int32_t grid;       /* blocks of the fused pass; 0 picks from the device and n.
+                           The persistent driver caps it at the number of blocks
+                           that fit on the device at once. */
     int32_t unroll;     /* 16-voxel chunks in flight per thread: 1 or 2 */
     int32_t driver;     /* FCM_DRIVER_* */
-    int32_t graph_k;    /* passes per host synchronisation (and per graph), 1..64 */
+    int32_t graph_k;    /* loop/graph drivers: passes per host synchronisation
+                           (and per graph), 1..64 */
+    int32_t exchange;   /* persistent driver: FCM_EXCHANGE_* */
 } fcm_tuning;
 
 typedef struct fcm_result {

@@ -28,6 +28,10 @@ FCM_F_KAHAN_ONLY = 1 << 0
 FCM_F_TIMING = 1 << 1
 FCM_DRIVER_LOOP = 0
 FCM_DRIVER_GRAPH = 1
+FCM_DRIVER_PERSISTENT = 2
+FCM_EXCHANGE_AUTO = 0
+FCM_EXCHANGE_LEADER = 1
+FCM_EXCHANGE_ALLGATHER = 2
 
 # every symbol include/fcm.h declares
 EXPORTS = (
@@ -55,6 +59,7 @@ class FcmTuning(ctypes.Structure):
         ("unroll", ctypes.c_int32),
         ("driver", ctypes.c_int32),
         ("graph_k", ctypes.c_int32),
+        ("exchange", ctypes.c_int32),
     ]
 
 

@@ -1,0 +1,1077 @@
+// gfx950 device code of the Fuzzy C-Means iteration (Sec. 2.1, Sec. 4 of the paper).
+// Templates shared by the per-cluster-count translation units fcm_pass_c*.hip.
+//
+// One fused streaming pass per iteration replaces the paper's per-cluster
+// kernel sequence (per-pixel numerator/denominator kernel, two shared-memory
+// reductions, a one-thread final sum, a membership kernel, Sec. 4.2-4.3):
+//
+//   pass p reads every voxel once (1 byte, 16-byte vector loads) and, in
+//   registers, evaluates U^p from v^p and -- for p >= 1 -- U^(p-1) from
+//   v^(p-1) (Eq.4), the per-voxel change max_j |u_j^p - u_j^(p-1)|, the
+//   weights a_j = (u_j^p)^m, the centroid sums sum a_j x and sum a_j (Eq.3)
+//   and the objective term sum_j a_j (x - v_j)^2 (Eq.1).  Memberships are
+//   never stored.  Per-thread sums use FP32 with Kahan compensation per
+//   16-voxel chunk; a block reduces them with wave64 DPP butterflies and an
+//   LDS step into one partial row.  The partial rows are reduced in a fixed
+//   order in FP64 -- or compensated FP32 -- into v^(p+1) (Eq.3), delta^p and
+//   J^p, and the stopping rule of Algorithm 1 is applied on the device.
+//
+// Two drivers share that pass:
+//   fcm_pass_kernel     one launch per pass; the last block to arrive (atomic
+//                       ticket) reduces the rows and updates the state.
+//   fcm_persist_kernel  one cooperative launch per solve (data range, v^0 and
+//                       every pass); one grid barrier per pass, after which
+//                       every block reduces all rows itself in the same order,
+//                       so all blocks hold bitwise identical centroids and the
+//                       same stopping decision without a second barrier.  Rows
+//                       alternate between two buffers by pass parity.  Every
+//                       barrier wait is bounded by a wall-clock limit and an
+//                       abort flag, so every wave always exits.
+//
+// Membership form for m = 2 (exact algebra of Eq.4): with q_k = (x - v_k)^2,
+// u_k = P_k / sum_j P_j where P_k = prod_{j != k} q_j, so one reciprocal
+// serves all C memberships; u_k q_k is the same for every k and equals the
+// voxel's objective term sum_k u_k^2 q_k.  Since u_k is proportional to
+// q_k^(-alpha), alpha = 1/(m-1), other m follow from the m = 2 memberships u2:
+// u_k = u2_k^alpha / sum_j u2_j^alpha (squares for m = 1.5, log2/exp2 else).
+//
+// Zero distances are exact: q_k = (x - v_k)^2 with no floor, so a voxel on a
+// centroid gets membership exactly 1 there and exactly 0 elsewhere, and a
+// cluster with no support keeps a zero denominator, as in the oracle.  The
+// product forms run only when every centroid of both sets lies in [0, 255]
+// with pairwise gaps >= 2^-6: then at most one q_k of a voxel is below 2^-14
+// and every leave-one-out product lies in [2^-98, 2^112], inside the normal
+// FP32 range.  Otherwise (coinciding or out-of-range centroids, a uniform
+// per-pass decision) the pass uses the normalised form
+// w_k = 2^(alpha (L_min - L_k)), L_k = log2 q_k clamped to [-1000, 256], which
+// gives exact zeros and the equal split over coinciding centroids.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fcm.h"
+#include "fcm_internal.h"
+
+namespace fcm {
+
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Sum over the 64 lanes of a fully active wave; every lane gets the same value.
+// Butterfly within rows of 16 (xor 1, xor 2, half-mirror, mirror), then the
+// four row sums in a fixed order.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_mov<0xB1>(v));
+    v = fmaxf(v, dpp_mov<0x4E>(v));
+    v = fmaxf(v, dpp_mov<0x141>(v));
+    v = fmaxf(v, dpp_mov<0x140>(v));
+    return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+// Kahan step: s + (-c) carries the running sum, c the lost low part.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Error-free sum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_coherent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Marks this block's arrival after its partial row is written; returns true
+// in every thread of the last block to arrive.
+__device__ __forceinline__ bool arrive_last(uint32_t* ticket) {
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x < 64) __threadfence();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// --- cross-block exchange of a cooperative launch ---------------------------
+//
+// Values travel as 64-bit words (round << 32) | payload, written and read with
+// relaxed agent-scope atomics.  A 64-bit access is single-copy atomic, so each
+// word proves by itself that it belongs to the current round: no flags, no
+// fences and no second load after a wait.  Round r: every block writes its
+// partial row as tagged words; block 0 polls the rows themselves, reduces,
+// decides and writes the tagged broadcast words; the other blocks poll those.
+// Every poll loop is bounded by a wall-clock limit; a timeout sets `abort`,
+// which every other poll also watches, so all blocks exit.  Tags of earlier
+// rounds never match (the round count only grows; buffers start zeroed).
+
+__device__ __forceinline__ uint64_t tagged(uint32_t round, uint32_t payload) {
+    return ((uint64_t)round << 32) | payload;
+}
+
+__device__ __forceinline__ void store_tagged(uint64_t* p, uint32_t round, uint32_t payload) {
+    __hip_atomic_store(p, tagged(round, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// one poll step's bookkeeping: true when the caller must give up
+__device__ __forceinline__ bool poll_expired(SyncState* sy, uint64_t t0, uint64_t limit_ticks) {
+    if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    if (wall_clock64() - t0 > limit_ticks) {
+        __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return false;
+}
+
+// Wait until the K words at src carry `round`; payloads into out.
+template <int K>
+__device__ __forceinline__ bool poll_tagged(const uint64_t* src, uint32_t round, uint32_t (&out)[K], SyncState* sy,
+                                            uint64_t t0, uint64_t limit_ticks) {
+    while (true) {
+        bool all = true;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const uint64_t w = __hip_atomic_load(src + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            all = all && (uint32_t)(w >> 32) == round;
+            out[r] = (uint32_t)w;
+        }
+        if (all) return true;
+        if (poll_expired(sy, t0, limit_ticks)) return false;
+    }
+}
+
+// Column-major float rows [rows][G] in plain memory (one launch per pass; the
+// last block reads them after the ticket's acquire).
+struct PlainRows {
+    float* P;
+    int G;
+    __device__ __forceinline__ void put(int r, float v) const { store_coherent(P + r * G + blockIdx.x, v); }
+    template <int K>
+    __device__ __forceinline__ bool get(int b, float (&v)[K]) const {
+#pragma unroll
+        for (int r = 0; r < K; ++r) v[r] = P[r * G + b];
+        return true;
+    }
+};
+
+// Row-major tagged rows [G][K] (cooperative launch).  A reader first polls the
+// row's last word, then loads the whole row and checks every tag.
+template <int K>
+struct TaggedRows {
+    uint64_t* W;
+    uint32_t round;
+    SyncState* sy;
+    uint64_t t0, limit;
+    __device__ __forceinline__ void put(int r, float v) const {
+        store_tagged(W + (size_t)blockIdx.x * K + r, round, __builtin_bit_cast(uint32_t, v));
+    }
+    __device__ __forceinline__ bool get(int b, float (&v)[K]) const {
+        const uint64_t* src = W + (size_t)b * K;
+        uint32_t last[1];
+        if (!poll_tagged<1>(src + K - 1, round, last, sy, t0, limit)) return false;
+        uint32_t raw[K];
+        if (!poll_tagged<K>(src, round, raw, sy, t0, limit)) return false;
+#pragma unroll
+        for (int r = 0; r < K; ++r) v[r] = __builtin_bit_cast(float, raw[r]);
+        return true;
+    }
+};
+
+// Broadcast of block 0's decision: C centroids and (next pass, done).
+template <int C>
+__device__ __forceinline__ void publish_decision(SyncState* sy, uint32_t round, const float* v, int p, int done) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) store_tagged(sy->bcw + k, round, __builtin_bit_cast(uint32_t, v[k]));
+    store_tagged(sy->bcw + C, round, ((uint32_t)p << 1) | (uint32_t)(done != 0));
+}
+
+template <int C>
+__device__ __forceinline__ bool await_decision(SyncState* sy, uint32_t round, uint64_t limit_ticks, float* v, int& p,
+                                               int& done) {
+    uint32_t raw[C + 1];
+    if (!poll_tagged<C + 1>(sy->bcw, round, raw, sy, wall_clock64(), limit_ticks)) return false;
+#pragma unroll
+    for (int k = 0; k < C; ++k) v[k] = __builtin_bit_cast(float, raw[k]);
+    p = (int)(raw[C] >> 1);
+    done = (int)(raw[C] & 1u);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// memberships of one voxel (Eq.4)
+// ---------------------------------------------------------------------------
+
+template <int C>
+__device__ __forceinline__ void sq_dist(float x, const float (&v)[C], float (&q)[C]) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const float d = x - v[k];
+        q[k] = d * d;
+    }
+}
+
+// log2 q clamped so that q = 0 maps to a finite floor far below any other level
+__device__ __forceinline__ float log2q(float q) {
+    return __builtin_amdgcn_fmed3f(__builtin_amdgcn_logf(q), -1000.0f, 256.0f);
+}
+
+// P_k = prod_{j != k} q_j from prefix and suffix products (3C - 6 products).
+template <int C>
+__device__ __forceinline__ void leave_one_out(const float (&q)[C], float (&P)[C]) {
+    float pre[C], suf[C];
+    pre[1] = q[0];
+#pragma unroll
+    for (int k = 2; k < C; ++k) pre[k] = pre[k - 1] * q[k - 1];
+    suf[C - 1] = q[C - 1];
+#pragma unroll
+    for (int k = C - 2; k >= 1; --k) suf[k] = q[k] * suf[k + 1];
+    P[0] = suf[1];
+    P[C - 1] = pre[C - 1];
+#pragma unroll
+    for (int k = 1; k < C - 1; ++k) P[k] = pre[k] * suf[k + 1];
+}
+
+struct Consts {
+    float alpha, mexp;
+};
+
+// Membership forms.  The three product forms need separated centroids in
+// [0, 255] (see the header comment); kNormLog works for any centroids.
+enum Form : int {
+    kProdM2 = 0,    // u = P / sum P                                  (m = 2)
+    kProdM15 = 1,   // u = u2^2 / sum u2^2, u2 the m = 2 memberships   (m = 1.5)
+    kProdPow = 2,   // u = u2^alpha / sum u2^alpha via log2/exp2        (other m)
+    kNormLog = 3,   // u = w / sum w, w = 2^(alpha (L_min - L)), L = log2 q
+};
+
+// m = 2 memberships from squared distances: u_k = P_k / sum_j P_j.
+template <int C>
+__device__ __forceinline__ void prod_u(const float (&q)[C], float (&u)[C]) {
+    float P[C];
+    leave_one_out<C>(q, P);
+    float S = P[0];
+#pragma unroll
+    for (int j = 1; j < C; ++j) S += P[j];
+    const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+    for (int j = 0; j < C; ++j) u[j] = P[j] * r;
+}
+
+// Memberships of one voxel (Eq.4) and, when FULL, a = u^m and the voxel's
+// objective term sum_j a_j q_j (Eq.1).  Working from u2 (in [0, 1], dominant
+// entries >= 1/C) keeps the log2/exp2 arguments of the other forms small.
+template <int C, int FORM, bool FULL>
+__device__ __forceinline__ void memb(float x, const float (&v)[C], const Consts& k, float (&u)[C], float (&a)[C],
+                                     float& Jv) {
+    float q[C];
+    sq_dist<C>(x, v, q);
+    if constexpr (FORM == kNormLog) {
+        float t[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) t[j] = log2q(q[j]);
+        float Lmin = t[0];
+#pragma unroll
+        for (int j = 1; j < C; ++j) Lmin = fminf(Lmin, t[j]);
+        float S = 0.f;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            t[j] = (Lmin - t[j]) * k.alpha;  // log2 w_j <= 0
+            u[j] = __builtin_amdgcn_exp2f(t[j]);
+            S += u[j];
+        }
+        const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+        for (int j = 0; j < C; ++j) u[j] *= r;
+        if constexpr (FULL) {
+            const float lS = __builtin_amdgcn_logf(S);
+            Jv = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                a[j] = __builtin_amdgcn_exp2f(k.mexp * (t[j] - lS));
+                Jv = fmaf(a[j], q[j], Jv);
+            }
+        }
+    } else {
+        float u2[C];
+        prod_u<C>(q, u2);
+        if constexpr (FORM == kProdM2) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] = u2[j];
+            if constexpr (FULL) {
+#pragma unroll
+                for (int j = 0; j < C; ++j) a[j] = u[j] * u[j];
+                Jv = u[0] * q[0];  // u_k q_k is the same for every k when m = 2
+            }
+        } else if constexpr (FORM == kProdM15) {
+            float S = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                u[j] = u2[j] * u2[j];
+                S += u[j];
+            }
+            const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] *= r;
+            if constexpr (FULL) {
+                Jv = 0.f;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    a[j] = u[j] * __builtin_amdgcn_sqrtf(u[j]);
+                    Jv = fmaf(a[j], q[j], Jv);
+                }
+            }
+        } else {
+            float t[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) t[j] = __builtin_amdgcn_fmed3f(__builtin_amdgcn_logf(u2[j]), -1000.0f, 0.0f);
+            float tmax = t[0];
+#pragma unroll
+            for (int j = 1; j < C; ++j) tmax = fmaxf(tmax, t[j]);
+            float S = 0.f;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                t[j] = (t[j] - tmax) * k.alpha;  // log2 w_j <= 0, max 0
+                u[j] = __builtin_amdgcn_exp2f(t[j]);
+                S += u[j];
+            }
+            const float r = __builtin_amdgcn_rcpf(S);
+#pragma unroll
+            for (int j = 0; j < C; ++j) u[j] *= r;
+            if constexpr (FULL) {
+                const float lS = __builtin_amdgcn_logf(S);
+                Jv = 0.f;
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    a[j] = __builtin_amdgcn_exp2f(k.mexp * (t[j] - lS));
+                    Jv = fmaf(a[j], q[j], Jv);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-thread accumulation
+// ---------------------------------------------------------------------------
+
+template <int C>
+struct Acc {
+    float ns[C], nc[C], ds[C], dc[C];
+    float js, jc, dmax;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < C; ++k) ns[k] = nc[k] = ds[k] = dc[k] = 0.f;
+        js = jc = dmax = 0.f;
+    }
+};
+
+template <int C>
+struct Group {
+    float n[C], d[C], j;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < C; ++k) n[k] = d[k] = 0.f;
+        j = 0.f;
+    }
+};
+
+template <int C, int FORM, bool OLD>
+__device__ __forceinline__ void voxel(float x, const float (&vn)[C], const float (&vo)[C], const Consts& k,
+                                      Group<C>& g, float& dmax) {
+    float u[C], a[C], Jv;
+    memb<C, FORM, true>(x, vn, k, u, a, Jv);
+    if constexpr (OLD) {
+        float uo[C], ao[C], Jo;
+        memb<C, FORM, false>(x, vo, k, uo, ao, Jo);
+#pragma unroll
+        for (int j = 0; j < C; ++j) dmax = fmaxf(dmax, fabsf(u[j] - uo[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        g.n[j] = fmaf(a[j], x, g.n[j]);
+        g.d[j] += a[j];
+    }
+    g.j += Jv;
+}
+
+template <int C>
+__device__ __forceinline__ void fold_group(Acc<C>& acc, const Group<C>& g) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        kahan_add(acc.ns[k], acc.nc[k], g.n[k]);
+        kahan_add(acc.ds[k], acc.dc[k], g.d[k]);
+    }
+    kahan_add(acc.js, acc.jc, g.j);
+}
+
+template <int C, int FORM, bool OLD>
+__device__ __forceinline__ void chunk16(uint4 w, const float (&vn)[C], const float (&vo)[C], const Consts& k,
+                                        Acc<C>& acc) {
+    Group<C> g;
+    g.zero();
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float x = (float)((words[i] >> (8 * b)) & 0xFFu);
+            voxel<C, FORM, OLD>(x, vn, vo, k, g, acc.dmax);
+        }
+    }
+    fold_group<C>(acc, g);
+}
+
+// Range and separation test of a centroid set for the product forms (uniform).
+template <int C>
+__device__ __forceinline__ bool separated(const float (&v)[C]) {
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        ok = ok && v[i] >= 0.0f && v[i] <= 255.0f;
+#pragma unroll
+        for (int j = i + 1; j < C; ++j) ok = ok && fabsf(v[i] - v[j]) >= 0.015625f;
+    }
+    return ok;
+}
+
+// The voxels of this thread for one pass.  `resident`: the thread owns at most
+// one 16-voxel chunk, already in `mine` (uniform across the grid).
+template <int C, int FORM, int UNROLL, bool OLD>
+__device__ __forceinline__ void pass_body(const PassArgs& a, const float (&vn)[C], const float (&vo)[C],
+                                          const Consts& kc, Acc<C>& acc, bool resident, uint4 mine) {
+    const int tid = threadIdx.x;
+    const uint4* body = reinterpret_cast<const uint4*>(a.x + a.head);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t c = (int64_t)blockIdx.x * kBlock + tid;
+    const int64_t nb = a.nbody;
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    if (resident) {
+        if (c < nb) chunk16<C, FORM, OLD>(mine, vn, vo, kc, acc);
+    } else if constexpr (UNROLL == 1) {
+        uint4 cur = c < nb ? body[c] : z;
+        while (c < nb) {
+            const int64_t cn = c + stride;
+            const uint4 nx = cn < nb ? body[cn] : z;
+            chunk16<C, FORM, OLD>(cur, vn, vo, kc, acc);
+            cur = nx;
+            c = cn;
+        }
+    } else {
+        uint4 c0 = c < nb ? body[c] : z;
+        uint4 c1 = c + stride < nb ? body[c + stride] : z;
+        while (c < nb) {
+            const int64_t cn = c + 2 * stride;
+            const uint4 n0 = cn < nb ? body[cn] : z;
+            const uint4 n1 = cn + stride < nb ? body[cn + stride] : z;
+            chunk16<C, FORM, OLD>(c0, vn, vo, kc, acc);
+            if (c + stride < nb) chunk16<C, FORM, OLD>(c1, vn, vo, kc, acc);
+            c0 = n0;
+            c1 = n1;
+            c = cn;
+        }
+    }
+    // unaligned head and tail (< 16 voxels each) go to block 0
+    if (blockIdx.x == 0) {
+        const int64_t tail0 = a.head + 16 * nb;
+        const int64_t nr = a.head + (a.n - tail0);
+        if (tid < nr) {
+            const int64_t i = tid < a.head ? (int64_t)tid : tail0 + (tid - a.head);
+            Group<C> g;
+            g.zero();
+            voxel<C, FORM, OLD>((float)a.x[i], vn, vo, kc, g, acc.dmax);
+            fold_group<C>(acc, g);
+        }
+    }
+}
+
+// Pass p of this block with the form chosen for the two centroid sets.
+template <int C, int MK, int UNROLL>
+__device__ __forceinline__ void run_pass(const PassArgs& a, int p, const float (&vn)[C], const float (&vo)[C],
+                                         Acc<C>& acc, bool resident, uint4 mine) {
+    constexpr int FAST = MK == kM2 ? kProdM2 : (MK == kM15 ? kProdM15 : kProdPow);
+    const Consts kc{a.alpha, a.mexp};
+    acc.zero();
+    if (separated<C>(vn) && (p == 0 || separated<C>(vo))) {
+        if (p == 0)
+            pass_body<C, FAST, UNROLL, false>(a, vn, vo, kc, acc, resident, mine);
+        else
+            pass_body<C, FAST, UNROLL, true>(a, vn, vo, kc, acc, resident, mine);
+    } else {
+        if (p == 0)
+            pass_body<C, kNormLog, UNROLL, false>(a, vn, vo, kc, acc, resident, mine);
+        else
+            pass_body<C, kNormLog, UNROLL, true>(a, vn, vo, kc, acc, resident, mine);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reductions across blocks: Eq.3 update and the stopping rule
+// ---------------------------------------------------------------------------
+
+// Block reduction of the thread sums into this block's partial row: wave
+// butterflies, then the waves in order (Kahan).  Row entries: for each k < C
+// num (sum, comp), den (sum, comp); then J (sum, comp); then max |dU|.
+template <int C, typename Rows>
+__device__ __forceinline__ void write_partial_row(const Acc<C>& acc, const Rows& rows) {
+    constexpr int NQ = 2 * C + 1;
+    __shared__ float s_red[kWaves][NQ + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    float f[NQ];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        f[k] = acc.ns[k] - acc.nc[k];
+        f[C + k] = acc.ds[k] - acc.dc[k];
+    }
+    f[2 * C] = acc.js - acc.jc;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float s = wave_sum(f[q]);
+        if (lane == 0) s_red[wid][q] = s;
+    }
+    const float m = wave_max(acc.dmax);
+    if (lane == 0) s_red[wid][NQ] = m;
+    __syncthreads();
+    if (tid < NQ) {
+        float s = 0.f, c = 0.f;
+        for (int w = 0; w < kWaves; ++w) kahan_add(s, c, s_red[w][tid]);
+        rows.put(2 * tid, s);
+        rows.put(2 * tid + 1, c);
+    } else if (tid == NQ) {
+        float mm = s_red[0][NQ];
+        for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_red[w][NQ]);
+        rows.put(2 * NQ, mm);
+    }
+}
+
+template <int C>
+struct Reduced {
+    double res[2 * C + 1];  // num[C], den[C], J
+    float dm;               // max |dU|
+};
+
+// Whole-block reduction of the G partial rows in a fixed order (thread t takes
+// rows t, t + blockDim, ...; then wave butterflies and the waves in order); the
+// result is written to `out` (shared) and valid in every thread after the
+// call.  Returns false in every thread if a row could not be obtained.
+template <int C, typename Rows>
+__device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>& out) {
+    constexpr int NQ = 2 * C + 1;
+    constexpr int R = partial_rows(C);
+    __shared__ double s_sum[kWaves][NQ];
+    __shared__ float s_lo[kWaves][NQ];
+    __shared__ float s_max[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    float dm = 0.f;
+    int bad = 0;
+    double acc[NQ];
+    float hi[NQ], lo[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        acc[q] = 0.0;
+        hi[q] = lo[q] = 0.f;
+    }
+    for (int b = tid; b < G; b += kBlock) {
+        float v[R];
+        if (!rows.get(b, v)) {
+            bad = 1;
+            break;
+        }
+        if (!kahan_only) {
+            // FP64 over the block partials, each taken as (sum - comp)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)v[2 * q] - (double)v[2 * q + 1];
+        } else {
+            // compensated FP32 throughout: (hi, lo) pairs combined error-free
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                float s, e;
+                two_sum(hi[q], v[2 * q], s, e);
+                hi[q] = s;
+                lo[q] += e - v[2 * q + 1];
+            }
+        }
+        dm = fmaxf(dm, v[R - 1]);
+    }
+    if (__syncthreads_or(bad)) return false;
+    if (!kahan_only) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double s = wave_sum_f64(acc[q]);
+            if (lane == 0) s_sum[wid][q] = s;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            for (int off = 1; off < 64; off <<= 1) {
+                const float oh = __shfl_xor(hi[q], off, 64);
+                const float ol = __shfl_xor(lo[q], off, 64);
+                float s, e;
+                // order the operands so both lanes of a pair compute the same bits
+                const bool low = (lane & off) == 0;
+                two_sum(low ? hi[q] : oh, low ? oh : hi[q], s, e);
+                lo[q] = (low ? lo[q] + ol : ol + lo[q]) + e;
+                hi[q] = s;
+            }
+            if (lane == 0) {
+                s_sum[wid][q] = (double)hi[q];
+                s_lo[wid][q] = lo[q];
+            }
+        }
+    }
+    const float m = wave_max(dm);
+    if (lane == 0) s_max[wid] = m;
+    __syncthreads();
+    if (tid < NQ) {
+        double r;
+        if (!kahan_only) {
+            r = s_sum[0][tid];
+            for (int w = 1; w < kWaves; ++w) r += s_sum[w][tid];
+        } else {
+            float h = (float)s_sum[0][tid], l = s_lo[0][tid];
+            for (int w = 1; w < kWaves; ++w) {
+                float s, e;
+                two_sum(h, (float)s_sum[w][tid], s, e);
+                h = s;
+                l += e + s_lo[w][tid];
+            }
+            r = (double)(h + l);
+        }
+        out.res[tid] = r;
+    } else if (tid == NQ) {
+        float mm = s_max[0];
+        for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_max[w]);
+        out.dm = mm;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Outcome of pass p (Eq.3 update and Algorithm 1's test), computed identically
+// by whoever calls it.
+template <int C>
+struct Step {
+    double vnext[C];
+    double delta, J;
+    int status, done;
+};
+
+template <int C>
+__device__ __forceinline__ void decide(const Reduced<C>& r, int p, const double* vcur, double eps, int max_iter,
+                                       Step<C>& s) {
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const double num = r.res[k], den = r.res[C + k];
+        s.vnext[k] = den > 0.0 ? num / den : vcur[k];
+        if (!isfinite(s.vnext[k])) bad = true;
+    }
+    s.J = r.res[2 * C];
+    if (!isfinite(s.J)) bad = true;
+    s.delta = p > 0 ? (double)r.dm : __builtin_nan("");
+    s.status = FCM_RUNNING;
+    s.done = 0;
+    if (bad) {
+        s.status = FCM_ENUMERIC;
+        s.done = 1;
+    } else if (p >= 1 && s.delta < eps) {
+        s.status = FCM_OK;
+        s.done = 1;
+    } else if (p >= max_iter) {
+        s.status = FCM_NOT_CONVERGED;
+        s.done = 1;
+    }
+}
+
+// Record pass p in the history and the state (one thread of one block).
+template <int C>
+__device__ __forceinline__ void commit(const PassArgs& a, int p, const double* vcur, const Step<C>& s) {
+    DevState* st = a.st;
+    a.hist_J[p] = s.J;
+    a.hist_d[p] = s.delta;
+#pragma unroll
+    for (int k = 0; k < C; ++k) st->vres[k] = vcur[k];
+    st->iters = p;
+    st->J = s.J;
+    st->delta = s.delta;
+    st->passes = p + 1;
+    if (!s.done) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            a.hist_v[(int64_t)(p + 1) * C + k] = s.vnext[k];
+            st->v32[(p + 1) & 1][k] = (float)s.vnext[k];
+        }
+        st->pass = p + 1;
+    }
+    st->status = s.status;
+    st->done = s.done;
+}
+
+// ---------------------------------------------------------------------------
+// driver 1: one launch per pass
+// ---------------------------------------------------------------------------
+
+template <int C, int MK, int UNROLL>
+__global__ __launch_bounds__(kBlock) void fcm_pass_kernel(PassArgs a) {
+    DevState* st = a.st;
+    if (st->done) return;
+    const int p = st->pass;
+    float vn[C], vo[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        vn[k] = st->v32[p & 1][k];
+        vo[k] = st->v32[(p + 1) & 1][k];
+    }
+    Acc<C> acc;
+    run_pass<C, MK, UNROLL>(a, p, vn, vo, acc, false, make_uint4(0u, 0u, 0u, 0u));
+    const int G = gridDim.x;
+    const PlainRows rows{a.partials, G};
+    write_partial_row<C>(acc, rows);
+    if (!arrive_last(&st->ticket)) return;
+    __shared__ Reduced<C> s_r;
+    reduce_rows<C>(rows, G, a.kahan_only, s_r);
+    if (threadIdx.x == 0) {
+        double vcur[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) vcur[k] = a.hist_v[(int64_t)p * C + k];
+        Step<C> s;
+        decide<C>(s_r, p, vcur, a.eps, a.max_iter, s);
+        commit<C>(a, p, vcur, s);
+        st->ticket = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// data range and initial centroids
+// ---------------------------------------------------------------------------
+
+// min and max grey level of this thread's voxels (grid-stride chunks + ragged)
+__device__ __forceinline__ void thread_minmax(const uint8_t* x, int64_t n, int64_t head, int64_t nbody,
+                                              uint32_t& lo, uint32_t& hi) {
+    const int tid = threadIdx.x;
+    const uint4* body = reinterpret_cast<const uint4*>(x + head);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + tid; c < nbody; c += stride) {
+        const uint4 w = body[c];
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t v = (words[i] >> (8 * b)) & 0xFFu;
+                lo = min(lo, v);
+                hi = max(hi, v);
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        const int64_t tail0 = head + 16 * nbody;
+        const int64_t nr = head + (n - tail0);
+        if (tid < nr) {
+            const int64_t i = tid < head ? (int64_t)tid : tail0 + (tid - head);
+            lo = min(lo, (uint32_t)x[i]);
+            hi = max(hi, (uint32_t)x[i]);
+        }
+    }
+}
+
+// block min/max; (lo, hi) is valid in thread 0 after the call
+__device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi) {
+    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    if (lane == 0) {
+        s_lo[wid] = lo;
+        s_hi[wid] = hi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+    }
+}
+
+// Whole-block reduction of the G (lo, hi) rows obtained through
+// get(b, lo_b, hi_b); valid in every thread after the call.  Returns false in
+// every thread if a row could not be obtained.
+template <typename Get>
+__device__ __forceinline__ bool reduce_minmax(const Get& get, int G, uint32_t& lo, uint32_t& hi) {
+    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    lo = 255u;
+    hi = 0u;
+    int bad = 0;
+    for (int b = tid; b < G; b += kBlock) {
+        uint32_t l, h;
+        if (!get(b, l, h)) {
+            bad = 1;
+            break;
+        }
+        lo = min(lo, l);
+        hi = max(hi, h);
+    }
+    if (__syncthreads_or(bad)) return false;
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    if (lane == 0) {
+        s_lo[wid] = lo;
+        s_hi[wid] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int w = 1; w < kWaves; ++w) {
+        lo = min(lo, s_lo[w]);
+        hi = max(hi, s_hi[w]);
+    }
+    __syncthreads();
+    return true;
+}
+
+// v^0 as FP64 holding FP32 values: given, or lo + k (hi - lo) / (C - 1) with the
+// product exact and the quotient and the sum rounded once each in FP64, then
+// rounded to FP32.
+__device__ __forceinline__ double initial_centroid(int k, int C, uint32_t lo, uint32_t hi, int given, const double* v0) {
+    float v32;
+    if (given) {
+        v32 = (float)v0[k];
+    } else {
+        const double v = (double)lo + (double)(k * (int)(hi - lo)) / (double)(C - 1);
+        v32 = (float)v;
+    }
+    return (double)v32;
+}
+
+// Write the start of a solve into the state (one thread).
+__device__ __forceinline__ void commit_start(DevState* st, double* hist_v, int C, uint32_t lo, uint32_t hi,
+                                             int given, const double* v0) {
+    for (int k = 0; k < kMaxC; ++k) {
+        float v32 = 0.f;
+        if (k < C) {
+            const double v = initial_centroid(k, C, lo, hi, given, v0);
+            v32 = (float)v;
+            hist_v[k] = v;
+        }
+        st->v32[0][k] = v32;
+        st->v32[1][k] = v32;
+        st->vres[k] = (double)v32;
+    }
+    st->lo = (int32_t)lo;
+    st->hi = (int32_t)hi;
+    st->pass = 0;
+    st->iters = -1;
+    st->passes = 0;
+    st->status = FCM_RUNNING;
+    st->delta = __builtin_nan("");
+    st->J = __builtin_nan("");
+    st->done = 0;
+}
+
+// ---------------------------------------------------------------------------
+// driver 2: one cooperative launch per solve
+// ---------------------------------------------------------------------------
+
+template <int C, int MK, int UNROLL>
+__global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
+    DevState* st = a.st;
+    SyncState* sy = &st->sync;
+    const int G = gridDim.x;
+    const int tid = threadIdx.x;
+    const bool leader = blockIdx.x == 0;
+    constexpr int R = partial_rows(C);
+    __shared__ double s_v64[C];
+    __shared__ float s_vn[C], s_vo[C];
+    __shared__ int s_p, s_done, s_ok;
+    if (tid == 0) s_ok = 1;
+    __shared__ Reduced<C> s_r;
+    // the last round of the previous launch (written by its block 0 before it
+    // ended); tags of this launch start above it
+    uint32_t round = __hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    if (a.do_init) {
+        uint32_t lo = 255u, hi = 0u;
+        thread_minmax(a.x, a.n, a.head, a.nbody, lo, hi);
+        block_minmax(lo, hi);
+        ++round;
+        uint64_t* mm = a.mm_rows + (size_t)(round & 1u) * 2 * G;
+        if (tid == 0) {
+            store_tagged(mm + 2 * blockIdx.x, round, lo);
+            store_tagged(mm + 2 * blockIdx.x + 1, round, hi);
+        }
+        if (leader || a.allgather) {
+            const uint64_t t0 = wall_clock64();
+            auto get = [&](int b, uint32_t& l, uint32_t& h) {
+                uint32_t raw[2];
+                if (!poll_tagged<2>(mm + 2 * b, round, raw, sy, t0, a.spin_ticks)) return false;
+                l = raw[0];
+                h = raw[1];
+                return true;
+            };
+            if (!reduce_minmax(get, G, lo, hi)) return;
+            if (tid < C) {
+                const double v = initial_centroid(tid, C, lo, hi, a.given, a.v0);
+                s_v64[tid] = v;
+                s_vn[tid] = (float)v;
+                s_vo[tid] = (float)v;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                s_p = 0;
+                s_done = 0;
+                if (leader) commit_start(st, a.hist_v, C, lo, hi, a.given, a.v0);
+                if (!a.allgather) publish_decision<C>(sy, round, s_vn, 0, 0);
+            }
+        } else {
+            if (tid == 0) {
+                float v[C];
+                int p = 0, done = 0;
+                s_ok = await_decision<C>(sy, round, a.spin_ticks, v, p, done);
+#pragma unroll
+                for (int k = 0; k < C; ++k) s_vn[k] = s_vo[k] = v[k];
+                s_p = p;
+                s_done = done;
+            }
+            __syncthreads();
+            if (!s_ok) return;
+        }
+    } else {
+        if (tid == 0) {
+            s_p = st->pass;
+            s_done = st->done;
+        }
+        __syncthreads();
+        if (tid < C) {
+            const int p = s_p;
+            s_v64[tid] = a.hist_v[(int64_t)p * C + tid];
+            s_vn[tid] = st->v32[p & 1][tid];
+            s_vo[tid] = st->v32[(p + 1) & 1][tid];
+        }
+    }
+    __syncthreads();
+
+    // the thread's only chunk stays in registers when the grid covers the data
+    const int64_t stride = (int64_t)G * kBlock;
+    const bool resident = a.nbody <= stride;
+    uint4 mine = make_uint4(0u, 0u, 0u, 0u);
+    {
+        const int64_t c = (int64_t)blockIdx.x * kBlock + tid;
+        if (resident && c < a.nbody) mine = reinterpret_cast<const uint4*>(a.x + a.head)[c];
+    }
+
+    for (int budget = a.max_passes; budget > 0 && !s_done; --budget) {
+        const int p = s_p;
+        float vn[C], vo[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            vn[k] = s_vn[k];
+            vo[k] = s_vo[k];
+        }
+        Acc<C> acc;
+        run_pass<C, MK, UNROLL>(a, p, vn, vo, acc, resident, mine);
+        ++round;
+        const TaggedRows<R> rows{a.rows + (size_t)(round & 1u) * R * G, round, sy, (uint64_t)wall_clock64(),
+                                 a.spin_ticks};
+        write_partial_row<C>(acc, rows);
+        if (leader || a.allgather) {
+            // every block of an all-gather launch reduces the same rows in the
+            // same order, so all hold bitwise identical results
+            if (!reduce_rows<C>(rows, G, a.kahan_only, s_r)) return;
+            if (tid == 0) {
+                double vcur[C];
+#pragma unroll
+                for (int k = 0; k < C; ++k) vcur[k] = s_v64[k];
+                Step<C> s;
+                decide<C>(s_r, p, vcur, a.eps, a.max_iter, s);
+                if (leader) commit<C>(a, p, vcur, s);
+                if (!s.done) {
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        s_vo[k] = s_vn[k];
+                        s_vn[k] = (float)s.vnext[k];
+                        s_v64[k] = s.vnext[k];
+                    }
+                    s_p = p + 1;
+                }
+                s_done = s.done;
+                if (!a.allgather) publish_decision<C>(sy, round, s_vn, s_p, s.done);
+            }
+        } else if (tid == 0) {
+            float v[C];
+            int pn = 0, done = 0;
+            s_ok = await_decision<C>(sy, round, a.spin_ticks, v, pn, done);
+            s_done = done;
+            if (s_ok && !done) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    s_vo[k] = s_vn[k];
+                    s_vn[k] = v[k];
+                }
+                s_p = pn;
+            }
+        }
+        __syncthreads();
+        if (!leader && !a.allgather && !s_ok) return;
+    }
+    if (leader && tid == 0) sy->gen = round;
+}
+
+}  // namespace fcm

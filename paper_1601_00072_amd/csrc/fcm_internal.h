@@ -10,9 +10,20 @@ namespace fcm {
 constexpr int kMaxC = 8;
 constexpr int kBlock = 256;          // threads per block of every streaming kernel
 constexpr int kMaxGrid = 8192;       // capacity of the partial-sum table
+constexpr int kMaxPersistGrid = 2048; // blocks of a cooperative launch
+
+// Cross-block exchange of the cooperative driver.  Zeroed when the handle is
+// created (and after an aborted solve), never by a reset: the round count only
+// grows, so tagged words of earlier rounds never match a later one.
+struct SyncState {
+    uint32_t gen;             // last round of the previous cooperative launch
+    uint32_t abort;           // set when a wait hit its time limit; every block then exits
+    uint64_t bcw[kMaxC + 1];  // block 0's decision: tagged centroids, then (next pass << 1 | done)
+};
 
 // Device-resident solver state.  Written only by the last block of a pass (or
-// of the data-range pass); read by every block at the start of the next one.
+// of the data-range pass), or by block 0 of a cooperative launch; read by every
+// block at the start of the next launch.
 struct DevState {
     int32_t pass;        // index p of the next fused pass (pass p computes U^p)
     int32_t done;        // nonzero once converged, out of iterations, or non-finite
@@ -25,6 +36,7 @@ struct DevState {
     double J;            // J_m(U^iters, v^iters)
     double vres[kMaxC];  // v^iters in FP64: the current result
     float v32[2][kMaxC]; // FP32 centroids used by the passes: v32[p & 1] = fl32(v^p)
+    SyncState sync;      // cooperative driver handshake (not cleared by a reset)
 };
 
 // Per-block partial row of a fused pass, stored column-major in a
@@ -50,6 +62,17 @@ struct PassArgs {
     float mexp;            // m
     int32_t max_iter;
     int32_t kahan_only;    // cross-block reduction in compensated FP32
+    // cooperative driver only
+    uint64_t* rows;        // [2][grid][rows] tagged partial rows, by round parity
+    uint64_t* mm_rows;     // [2][grid][2] tagged per-block grey-level range, by round parity
+    int32_t allgather;     // every block reduces all rows (else block 0 reduces and broadcasts)
+    int32_t pad2;
+    int32_t do_init;       // run the data-range pass and set v^0 first
+    int32_t given;         // v^0 = v0 below instead of evenly spaced
+    double v0[kMaxC];
+    int32_t max_passes;    // passes this launch may run
+    int32_t pad;
+    uint64_t spin_ticks;   // wall-clock limit of one wait
 };
 
 struct InitArgs {
@@ -73,10 +96,14 @@ struct LabelArgs {
     int32_t bytewise;      // x and labels differ in 16-byte alignment
 };
 
-// Launchers (fcm_kernels.hip).  Return hipSuccess or the launch error.
+using PassFn = void (*)(PassArgs);
+
+// Launchers (fcm_common.hip, fcm_dispatch.hip).  Return hipSuccess or the launch error.
 hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int C, int mclass, int unroll, int grid, hipStream_t s);
 hipError_t launch_labels(const LabelArgs& a, int grid, hipStream_t s);
 bool pass_supported(int C, int mclass, int unroll);
+hipError_t persist_max_grid(int C, int mclass, int unroll, int ncu, int* max_grid);
+hipError_t launch_persist(const PassArgs& a, int C, int mclass, int unroll, int grid, hipStream_t s);
 
 }  // namespace fcm

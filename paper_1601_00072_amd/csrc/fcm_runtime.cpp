@@ -3,15 +3,17 @@
 // The paper's host side (Sec. 4.1-4.3) allocates 1-D device arrays, loops on
 // the host, copies the whole membership matrix back every iteration to test
 // convergence, and defuzzifies on the host.  Here the host only validates,
-// owns the workspace and launches passes in batches; the stopping test, the
-// centroid update and the defuzzification table run on the device, and the
-// host reads back a ~200-byte state record once per batch.
+// owns the workspace and launches work; the stopping test, the centroid
+// update and the defuzzification table run on the device, and the host reads
+// back a ~250-byte state record once per batch of passes (once per solve with
+// the persistent driver).
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -39,6 +41,8 @@ int dev_err(hipError_t e, const char* what) {
 
 constexpr uint32_t kKnownFlags = FCM_F_KAHAN_ONLY | FCM_F_TIMING;
 constexpr int kMaxGraphK = 64;
+constexpr double kBarrierLimitSeconds = 5.0;
+constexpr int64_t kAllGatherBytes = 12LL << 20;
 
 int validate_params(const fcm_params* p) {
     if (!p) return FCM_EINVAL;
@@ -62,8 +66,10 @@ int validate_tuning(const fcm_tuning* t) {
     if (t->block != kBlock) return FCM_EINVAL;
     if (t->grid < 0 || t->grid > kMaxGrid) return FCM_EINVAL;
     if (t->unroll != 1 && t->unroll != 2) return FCM_EINVAL;
-    if (t->driver != FCM_DRIVER_LOOP && t->driver != FCM_DRIVER_GRAPH) return FCM_EINVAL;
+    if (t->driver != FCM_DRIVER_LOOP && t->driver != FCM_DRIVER_GRAPH && t->driver != FCM_DRIVER_PERSISTENT)
+        return FCM_EINVAL;
     if (t->graph_k < 1 || t->graph_k > kMaxGraphK) return FCM_EINVAL;
+    if (t->exchange < FCM_EXCHANGE_AUTO || t->exchange > FCM_EXCHANGE_ALLGATHER) return FCM_EINVAL;
     return FCM_OK;
 }
 
@@ -77,16 +83,23 @@ struct fcm_handle {
     hipStream_t stream = nullptr;
     int device = 0;
     int ncu = 256;
+    int coop = 0;               // cooperative launches supported
+    uint64_t spin_ticks = 0;    // barrier wait limit in wall-clock ticks
     int mclass = kM2;
     float alpha = 1.f, mexp = 2.f;
 
     DevState* d_state = nullptr;
-    float* d_partials = nullptr;
-    double* d_hist = nullptr;   // v: (max_iter + 2) * C, then delta, then J: (max_iter + 2) each
+    float* d_partials = nullptr;   // [rows][grid] partial rows of the per-pass launches
+    uint32_t* d_minmax = nullptr;  // [2][grid]
+    uint64_t* d_rows = nullptr;    // [2][kMaxPersistGrid][rows] tagged partial rows (cooperative driver)
+    uint64_t* d_mmrows = nullptr;  // [2][kMaxPersistGrid][2] tagged grey-level ranges (cooperative driver)
+    bool aborted = false;          // a cooperative wait timed out; the next reset clears everything
+    double* d_hist = nullptr;      // v: (max_iter + 2) * C, then delta, then J: (max_iter + 2) each
     DevState* h_state = nullptr;
 
     fcm_tuning tun{};
-    int grid = 1;               // resolved pass grid
+    int grid = 1;               // resolved grid of the current driver
+    bool pending_init = true;   // the data-range pass has not run since init/reset
 
     hipStream_t cap = nullptr;  // capture-only stream for the graph driver
     hipGraph_t graph = nullptr;
@@ -96,7 +109,6 @@ struct fcm_handle {
 
     std::vector<hipEvent_t> ev;
     double kernel_ms = 0.0;
-    bool state_valid = false;
 
     double* hist_v() const { return d_hist; }
     double* hist_d() const { return d_hist + (int64_t)(p.max_iter + 2) * p.n_clusters; }
@@ -105,12 +117,17 @@ struct fcm_handle {
 
 namespace {
 
-int resolve_grid(const fcm_handle* h) {
-    if (h->tun.grid > 0) return h->tun.grid;
-    // one 16-voxel chunk per thread at least, at most 4 blocks per CU
-    int64_t want = (h->nbody + kBlock - 1) / kBlock;
-    int64_t cap = 4LL * h->ncu;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, cap), kMaxGrid));
+int64_t chunk_blocks(const fcm_handle* h) { return (h->nbody + kBlock - 1) / kBlock; }
+
+int resolve_grid(fcm_handle* h, int* out) {
+    int64_t want = h->tun.grid > 0 ? h->tun.grid : std::min<int64_t>(chunk_blocks(h), 4LL * h->ncu);
+    if (h->tun.driver == FCM_DRIVER_PERSISTENT) {
+        int cap = 0;
+        FCM_HIP(persist_max_grid(h->p.n_clusters, h->mclass, h->tun.unroll, h->ncu, &cap));
+        want = std::min<int64_t>(want, std::min(cap, kMaxPersistGrid));
+    }
+    *out = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxGrid));
+    return FCM_OK;
 }
 
 PassArgs pass_args(const fcm_handle* h) {
@@ -129,6 +146,17 @@ PassArgs pass_args(const fcm_handle* h) {
     a.mexp = h->mexp;
     a.max_iter = h->p.max_iter;
     a.kahan_only = (h->p.flags & FCM_F_KAHAN_ONLY) ? 1 : 0;
+    a.rows = h->d_rows;
+    a.mm_rows = h->d_mmrows;
+    // all-gather while the rows every block reads stay small (grid^2 rows)
+    a.allgather = (int64_t)h->grid * h->grid * partial_rows(h->p.n_clusters) * 8 <= kAllGatherBytes ? 1 : 0;
+    if (h->tun.exchange == FCM_EXCHANGE_LEADER) a.allgather = 0;
+    if (h->tun.exchange == FCM_EXCHANGE_ALLGATHER) a.allgather = 1;
+    a.do_init = h->pending_init ? 1 : 0;
+    a.given = h->p.init == FCM_INIT_GIVEN ? 1 : 0;
+    for (int k = 0; k < kMaxC; ++k) a.v0[k] = h->given[k];
+    a.max_passes = 0;
+    a.spin_ticks = h->spin_ticks;
     return a;
 }
 
@@ -165,7 +193,11 @@ int build_graph(fcm_handle* h) {
 int read_state(fcm_handle* h) {
     FCM_HIP(hipMemcpyAsync(h->h_state, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     FCM_HIP(hipStreamSynchronize(h->stream));
-    h->state_valid = true;
+    if (h->h_state->sync.abort) {
+        h->aborted = true;
+        g_last_error = "a cross-block wait exceeded its time limit; the solve was aborted (reset the handle)";
+        return FCM_EDEVICE;
+    }
     return FCM_OK;
 }
 
@@ -184,26 +216,78 @@ void fill_result(const fcm_handle* h, fcm_result* out) {
     out->hi = s.hi;
 }
 
-// Launch up to `batch` passes and read the state back once.
+int ensure_events(fcm_handle* h, int count) {
+    while ((int)h->ev.size() < count) {
+        hipEvent_t e;
+        FCM_HIP(hipEventCreate(&e));
+        h->ev.push_back(e);
+    }
+    return FCM_OK;
+}
+
+// The data-range pass as its own launch (loop and graph drivers, and any call
+// that needs v^0 before a pass has run).
+int flush_init(fcm_handle* h) {
+    if (!h->pending_init) return FCM_OK;
+    InitArgs ia{};
+    ia.x = h->d_x;
+    ia.n = h->n;
+    ia.head = h->head;
+    ia.nbody = h->nbody;
+    ia.st = h->d_state;
+    ia.partials = h->d_minmax;
+    ia.hist_v = h->hist_v();
+    ia.C = h->p.n_clusters;
+    ia.given = h->p.init == FCM_INIT_GIVEN ? 1 : 0;
+    for (int k = 0; k < h->p.n_clusters; ++k) ia.v0[k] = h->given[k];
+    const int igrid = (int)std::max<int64_t>(1, std::min<int64_t>(chunk_blocks(h), std::min<int64_t>(4LL * h->ncu,
+                                                                                                      kMaxGrid)));
+    hipError_t e = launch_init(ia, igrid, h->stream);
+    if (e != hipSuccess) return dev_err(e, "launch_init");
+    h->pending_init = false;
+    return FCM_OK;
+}
+
+// Run up to `batch` passes and read the state back once.
 int run_batch(fcm_handle* h, int batch) {
     const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
-    const int before = h->h_state->passes;
+    if (h->tun.driver == FCM_DRIVER_PERSISTENT) {
+        PassArgs a = pass_args(h);
+        a.max_passes = batch;
+        if (timing) {
+            int rc = ensure_events(h, 2);
+            if (rc != FCM_OK) return rc;
+            FCM_HIP(hipEventRecord(h->ev[0], h->stream));
+        }
+        hipError_t e = launch_persist(a, h->p.n_clusters, h->mclass, h->tun.unroll, h->grid, h->stream);
+        if (e != hipSuccess) return dev_err(e, "hipLaunchCooperativeKernel");
+        h->pending_init = false;
+        if (timing) FCM_HIP(hipEventRecord(h->ev[1], h->stream));
+        int rc = read_state(h);
+        if (rc != FCM_OK) return rc;
+        if (timing) {
+            float ms = 0.f;
+            FCM_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+            h->kernel_ms += ms;
+        }
+        return FCM_OK;
+    }
+    int rc = flush_init(h);
+    if (rc != FCM_OK) return rc;
     if (!timing && h->tun.driver == FCM_DRIVER_GRAPH && batch == h->tun.graph_k) {
         if (!h->gexec || h->graph_k != h->tun.graph_k || h->graph_grid != h->grid ||
             h->graph_unroll != h->tun.unroll) {
-            int rc = build_graph(h);
+            rc = build_graph(h);
             if (rc != FCM_OK) return rc;
         }
         FCM_HIP(hipGraphLaunch(h->gexec, h->stream));
         return read_state(h);
     }
+    const int before = h->h_state->passes;
     const PassArgs a = pass_args(h);
     if (timing) {
-        while ((int)h->ev.size() < 2 * batch) {
-            hipEvent_t e;
-            FCM_HIP(hipEventCreate(&e));
-            h->ev.push_back(e);
-        }
+        rc = ensure_events(h, 2 * batch);
+        if (rc != FCM_OK) return rc;
     }
     for (int i = 0; i < batch; ++i) {
         if (timing) FCM_HIP(hipEventRecord(h->ev[2 * i], h->stream));
@@ -211,7 +295,7 @@ int run_batch(fcm_handle* h, int batch) {
         if (e != hipSuccess) return dev_err(e, "launch_pass");
         if (timing) FCM_HIP(hipEventRecord(h->ev[2 * i + 1], h->stream));
     }
-    int rc = read_state(h);
+    rc = read_state(h);
     if (rc != FCM_OK) return rc;
     if (timing) {
         const int ran = std::min(batch, h->h_state->passes - before);
@@ -224,28 +308,31 @@ int run_batch(fcm_handle* h, int batch) {
     return FCM_OK;
 }
 
+// Clear the device state and mark the data-range pass as pending.  The
+// cooperative exchange state is kept (its round count only grows) unless a
+// wait was aborted, which clears it together with the tagged row buffers.
 int enqueue_start(fcm_handle* h) {
-    FCM_HIP(hipMemsetAsync(h->d_state, 0, sizeof(DevState), h->stream));
-    InitArgs ia{};
-    ia.x = h->d_x;
-    ia.n = h->n;
-    ia.head = h->head;
-    ia.nbody = h->nbody;
-    ia.st = h->d_state;
-    ia.partials = reinterpret_cast<uint32_t*>(h->d_partials);
-    ia.hist_v = h->hist_v();
-    ia.C = h->p.n_clusters;
-    ia.given = h->p.init == FCM_INIT_GIVEN ? 1 : 0;
-    for (int k = 0; k < h->p.n_clusters; ++k) ia.v0[k] = h->given[k];
-    const int igrid = (int)std::max<int64_t>(1, std::min<int64_t>((h->nbody + kBlock - 1) / kBlock,
-                                                                    std::min<int64_t>(4LL * h->ncu, kMaxGrid)));
-    hipError_t e = launch_init(ia, igrid, h->stream);
-    if (e != hipSuccess) return dev_err(e, "launch_init");
+    if (h->aborted) {
+        FCM_HIP(hipMemsetAsync(h->d_state, 0, sizeof(DevState), h->stream));
+        FCM_HIP(hipMemsetAsync(h->d_rows, 0, sizeof(uint64_t) * 2 * kMaxPersistGrid * partial_rows(kMaxC), h->stream));
+        FCM_HIP(hipMemsetAsync(h->d_mmrows, 0, sizeof(uint64_t) * 4 * kMaxPersistGrid, h->stream));
+        h->aborted = false;
+    } else {
+        FCM_HIP(hipMemsetAsync(h->d_state, 0, offsetof(DevState, sync), h->stream));
+    }
     std::memset(h->h_state, 0, sizeof(DevState));
     h->h_state->iters = -1;
     h->h_state->status = FCM_RUNNING;
     h->kernel_ms = 0.0;
+    h->pending_init = true;
     return FCM_OK;
+}
+
+// State as of the last completed work, running the data-range pass first if needed.
+int sync_state(fcm_handle* h) {
+    int rc = flush_init(h);
+    if (rc != FCM_OK) return rc;
+    return read_state(h);
 }
 
 void release(fcm_handle* h) {
@@ -255,6 +342,9 @@ void release(fcm_handle* h) {
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->d_state) (void)hipFree(h->d_state);
     if (h->d_partials) (void)hipFree(h->d_partials);
+    if (h->d_minmax) (void)hipFree(h->d_minmax);
+    if (h->d_rows) (void)hipFree(h->d_rows);
+    if (h->d_mmrows) (void)hipFree(h->d_mmrows);
     if (h->d_hist) (void)hipFree(h->d_hist);
     if (h->h_state) (void)hipHostFree(h->h_state);
     delete h;
@@ -264,7 +354,7 @@ void release(fcm_handle* h) {
 
 extern "C" {
 
-int fcm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+int fcm_version(void) { return 1 * 10000 + 1 * 100 + 0; }
 
 const char* fcm_strerror(int status) {
     switch (status) {
@@ -312,19 +402,30 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     if ((e = hipGetDevice(&h->device)) != hipSuccess) return fail(dev_err(e, "hipGetDevice"));
     if ((e = hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess)
         return fail(dev_err(e, "hipDeviceGetAttribute"));
+    if (hipDeviceGetAttribute(&h->coop, hipDeviceAttributeCooperativeLaunch, h->device) != hipSuccess) h->coop = 0;
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clock_khz <= 0)
+        clock_khz = 100000;
+    h->spin_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
     h->tun.block = kBlock;
     h->tun.grid = 0;
     h->tun.unroll = 1;
-    h->tun.driver = FCM_DRIVER_GRAPH;
+    h->tun.driver = h->coop ? FCM_DRIVER_PERSISTENT : FCM_DRIVER_GRAPH;
     h->tun.graph_k = 8;
-    h->grid = resolve_grid(h);
+    h->tun.exchange = FCM_EXCHANGE_AUTO;
+    if ((rc = resolve_grid(h, &h->grid)) != FCM_OK) return fail(rc);
 
     if (hipMalloc(&h->d_state, sizeof(DevState)) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipMalloc(&h->d_partials, sizeof(float) * partial_rows(kMaxC) * kMaxGrid) != hipSuccess)
         return fail(FCM_ENOMEM);
+    if (hipMalloc(&h->d_minmax, sizeof(uint32_t) * 2 * kMaxGrid) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&h->d_rows, sizeof(uint64_t) * 2 * kMaxPersistGrid * partial_rows(kMaxC)) != hipSuccess)
+        return fail(FCM_ENOMEM);
+    if (hipMalloc(&h->d_mmrows, sizeof(uint64_t) * 4 * kMaxPersistGrid) != hipSuccess) return fail(FCM_ENOMEM);
     const size_t hist_doubles = (size_t)(p->max_iter + 2) * (C + 2);
     if (hipMalloc(&h->d_hist, sizeof(double) * hist_doubles) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) return fail(FCM_ENOMEM);
+    h->aborted = true;  // first start clears the handshake and the flags too
     rc = enqueue_start(h);
     if (rc != FCM_OK) return fail(rc);
     *out = h;
@@ -341,8 +442,16 @@ int fcm_set_tuning(fcm_handle* h, const fcm_tuning* t) {
     int rc = validate_tuning(t);
     if (rc != FCM_OK) return rc;
     if (!pass_supported(h->p.n_clusters, h->mclass, t->unroll)) return FCM_EUNSUPPORTED;
+    if (t->driver == FCM_DRIVER_PERSISTENT && !h->coop) return FCM_EUNSUPPORTED;
+    const fcm_tuning old = h->tun;
     h->tun = *t;
-    h->grid = resolve_grid(h);
+    int grid = 1;
+    rc = resolve_grid(h, &grid);
+    if (rc != FCM_OK) {
+        h->tun = old;
+        return rc;
+    }
+    h->grid = grid;
     return FCM_OK;
 }
 
@@ -355,14 +464,18 @@ int fcm_get_tuning(const fcm_handle* h, fcm_tuning* t) {
 
 int fcm_iterate(fcm_handle* h, int32_t k, fcm_result* out) {
     if (!h || !out || k < 0) return FCM_EINVAL;
-    int rc = read_state(h);
+    int rc = h->pending_init ? FCM_OK : read_state(h);
     if (rc != FCM_OK) return rc;
     int remaining = k;
-    while (remaining > 0 && !h->h_state->done) {
-        const int batch = std::min(remaining, h->tun.graph_k);
+    while (remaining > 0 && (h->pending_init || !h->h_state->done)) {
+        const int batch = h->tun.driver == FCM_DRIVER_PERSISTENT ? remaining : std::min(remaining, h->tun.graph_k);
         rc = run_batch(h, batch);
         if (rc != FCM_OK) return rc;
         remaining -= batch;
+    }
+    if (h->pending_init) {
+        rc = sync_state(h);
+        if (rc != FCM_OK) return rc;
     }
     fill_result(h, out);
     return out->status;
@@ -370,15 +483,17 @@ int fcm_iterate(fcm_handle* h, int32_t k, fcm_result* out) {
 
 int fcm_solve(fcm_handle* h, fcm_result* out) {
     if (!h || !out) return FCM_EINVAL;
-    int rc = read_state(h);
+    int rc = h->pending_init ? FCM_OK : read_state(h);
     if (rc != FCM_OK) return rc;
     // every pass either finishes the solve or advances the pass index, so
     // max_iter + 1 passes always suffice; the bound guards the host loop
-    int64_t budget = (int64_t)h->p.max_iter + 1 + h->tun.graph_k;
-    while (!h->h_state->done && budget > 0) {
-        rc = run_batch(h, h->tun.graph_k);
+    const int64_t total = (int64_t)h->p.max_iter + 1;
+    int64_t budget = total + h->tun.graph_k;
+    while ((h->pending_init || !h->h_state->done) && budget > 0) {
+        const int batch = h->tun.driver == FCM_DRIVER_PERSISTENT ? (int)total : h->tun.graph_k;
+        rc = run_batch(h, batch);
         if (rc != FCM_OK) return rc;
-        budget -= h->tun.graph_k;
+        budget -= batch;
     }
     fill_result(h, out);
     return out->status;
@@ -386,6 +501,8 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
 
 int fcm_labels(fcm_handle* h, uint8_t* d_labels) {
     if (!h || !d_labels) return FCM_EINVAL;
+    int rc = flush_init(h);
+    if (rc != FCM_OK) return rc;
     LabelArgs a{};
     a.x = h->d_x;
     a.labels = d_labels;
@@ -406,7 +523,7 @@ int fcm_labels(fcm_handle* h, uint8_t* d_labels) {
 
 int fcm_centroids(fcm_handle* h, double* out) {
     if (!h || !out) return FCM_EINVAL;
-    int rc = read_state(h);
+    int rc = sync_state(h);
     if (rc != FCM_OK) return rc;
     for (int k = 0; k < h->p.n_clusters; ++k) out[k] = h->h_state->vres[k];
     return FCM_OK;
@@ -414,7 +531,7 @@ int fcm_centroids(fcm_handle* h, double* out) {
 
 int fcm_trajectory(fcm_handle* h, int32_t t, double* v_out, double* delta, double* J) {
     if (!h) return FCM_EINVAL;
-    int rc = read_state(h);
+    int rc = sync_state(h);
     if (rc != FCM_OK) return rc;
     if (t < 0 || t > h->h_state->iters) return FCM_EINVAL;
     const int C = h->p.n_clusters;

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.fcm_version() == 10000
+    assert lib.fcm_version() == 10100
     for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert lib.fcm_strerror(code)
     assert lib.fcm_strerror(12345) == b"unknown status"
@@ -91,7 +91,7 @@ def test_init_rejects_bad_pointers_and_sizes(lib):
 
 def test_null_handle_calls(lib):
     r = L.FcmResult()
-    t = L.FcmTuning(block=256, grid=0, unroll=1, driver=1, graph_k=8)
+    t = L.FcmTuning(block=256, grid=0, unroll=1, driver=1, graph_k=8, exchange=0)
     buf = (ctypes.c_double * 8)()
     assert lib.fcm_iterate(None, 1, ctypes.byref(r)) == L.FCM_EINVAL
     assert lib.fcm_solve(None, ctypes.byref(r)) == L.FCM_EINVAL

@@ -50,9 +50,10 @@ def check_against_literal(torch_dev, x, C, m=2.0, eps=1e-5, max_iter=300, init=N
     v0 = None if init is None else np.asarray(init, dtype=np.float64).astype(np.float32).astype(np.float64)
     ora = fcm_ref.solve(x, C, m, eps, max_iter, v0=v0)
     assert res.status in (0, 1)
-    matched = P.check_iterations(res, ora, eps)
-    if not matched or len(ora.v) <= res.iters:
-        ora = fcm_ref.solve(x, C, m, 0.0, res.iters, v0=ora.v[0])
+    if res.iters != ora.T:
+        ora_ext = fcm_ref.solve(x, C, m, 0.0, max(res.iters, ora.T) + 1, v0=ora.v[0])
+        P.check_iterations(res, ora.T, ora_ext, eps)
+        ora = ora_ext
     err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     assert res.passes == res.iters + 1
@@ -93,18 +94,21 @@ def test_ragged_sizes_and_offsets(torch_dev, n, offset):
     check_against_literal(torch_dev, x, 4)
 
 
+@pytest.mark.parametrize("driver,exchange", [(0, 0), (2, 1), (2, 2)])
 @pytest.mark.parametrize("grid,unroll", [(1, 1), (3, 2), (77, 1), (256, 2), (1024, 1), (4096, 2)])
-def test_launch_shapes(torch_dev, grid, unroll):
-    announce("launch grid", grid, "unroll", unroll)
+def test_launch_shapes(torch_dev, grid, unroll, driver, exchange):
+    announce("launch grid", grid, "unroll", unroll, "driver", driver, "exchange", exchange)
     x = phantom_2d(300, 333, seed=4)
-    check_against_literal(torch_dev, x, 4, tuning=dict(grid=grid, unroll=unroll))
+    check_against_literal(torch_dev, x, 4, tuning=dict(grid=grid, unroll=unroll, driver=driver, exchange=exchange))
 
 
-@pytest.mark.parametrize("driver,k", [(0, 1), (0, 5), (1, 1), (1, 3), (1, 16)])
-def test_drivers(torch_dev, driver, k):
-    announce("driver", driver, "graph_k", k)
-    x = phantom_2d(200, 200, seed=1)
-    check_against_literal(torch_dev, x, 4, tuning=dict(driver=driver, graph_k=k))
+@pytest.mark.parametrize("driver,k,exchange", [(0, 1, 0), (0, 5, 0), (1, 1, 0), (1, 3, 0), (1, 16, 0), (2, 1, 0),
+                                               (2, 1, 1), (2, 1, 2)])
+@pytest.mark.parametrize("shape", [(200, 200), (32, 160, 160)])
+def test_drivers(torch_dev, driver, k, exchange, shape):
+    announce("driver", driver, "graph_k", k, "exchange", exchange, "shape", shape)
+    x = phantom(PhantomParams(shape=shape, seed=1))
+    check_against_literal(torch_dev, x, 4, tuning=dict(driver=driver, graph_k=k, exchange=exchange))
 
 
 # --- cluster counts and fuzziness -------------------------------------------
@@ -199,14 +203,17 @@ def test_bitwise_deterministic(torch_dev):
     assert np.array_equal(a[2], b[2])
 
 
-def test_iterate_in_steps_equals_solve(torch_dev):
-    announce("iterate steps")
+@pytest.mark.parametrize("driver", [0, 1, 2])
+def test_iterate_in_steps_equals_solve(torch_dev, driver):
+    announce("iterate steps, driver", driver)
     torch, dev = torch_dev
     from paper_1601_00072_amd import FCM
     x = torch.from_numpy(phantom_2d(200, 200, seed=1).ravel()).to(dev)
     with FCM(x, 4) as f:
+        f.set_tuning(driver=driver)
         full = f.solve()
     with FCM(x, 4) as f:
+        f.set_tuning(driver=driver)
         seen = []
         while True:
             r = f.iterate(1)
@@ -249,9 +256,10 @@ def check_against_levels(torch_dev, x, C, m, eps=1e-5, **kw):
     res, traj, lab = run_gpu(torch_dev, x, C, m, eps, **kw)
     h = fcm_hist.histogram(x)
     ora = fcm_hist.solve(h, C, m, eps, 300)
-    matched = P.check_iterations(res, ora, eps)
-    if not matched or len(ora.v) <= res.iters:
-        ora = fcm_hist.solve(h, C, m, 0.0, res.iters, v0=ora.v[0])
+    if res.iters != ora.T:
+        ora_ext = fcm_hist.solve(h, C, m, 0.0, max(res.iters, ora.T) + 1, v0=ora.v[0])
+        P.check_iterations(res, ora.T, ora_ext, eps)
+        ora = ora_ext
     err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     return res, err, amb
