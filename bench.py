@@ -1,22 +1,24 @@
 """Benchmark of the FCM hot path on one MI355X.
 
-A step is one whole solve on a resident input: the data-range pass and v^0
-(init), fused passes until max |dU| < eps, and the defuzzified labels.
-Workload: the 128x128x64 (1,048,576-voxel) ellipsoid-shell phantom, seed 2,
-C = 4, m = 2, eps = 1e-5, max 300 iterations.
+A step is one whole solve on a resident input: the data-range pass and v^0,
+fused passes until max |dU| < eps, and the defuzzified labels.  Headline
+workload: the 128x128x64 (1,048,576-voxel) ellipsoid-shell phantom, seed 2,
+sigma 8, bias 10 %, C = 4, m = 2, eps = 1e-5, max 300 iterations.
 
-Prints one JSON line.  ``value`` = voxel-iterations/s = N * passes / wall time
+Prints one JSON line.  ``value`` = voxel-iterations/s = n * passes / wall time
 of the timed steps (passes = T + 1 per solve).  ``roofline`` refers to the
-fused pass kernel: algorithmic VALU lane-ops per voxel-iteration (see
-``alg_lane_ops``) times the voxels and passes of a launch, over the pass's
-average duration measured with HIP events on the solve's stream.
+dominant kernel, the persistent solve kernel (one launch per solve runs the
+data-range pass and every fused pass): algorithmic VALU lane-ops per voxel and
+pass (``alg_lane_ops``) times the voxels and passes of a launch, over the
+launch's average duration from HIP events recorded on the solve's stream.
 ``cpu_baseline`` is the FP64 oracle timed on the host on the same volume.
+``extra`` holds two further measured workloads (the 512x512x256 volume and the
+512-instance batch against a per-instance loop); ``--quick`` skips them.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +31,7 @@ sys.path.insert(0, ROOT)
 # quarter rate, i.e. 4 lane-op slots each.
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # 3.93e13 lane-op/s
 HBM_PEAK = 8.0e12
+METRIC = "FCM voxel-iterations/s & time-to-converge (eps=1e-5) vs plain init, % roofline"
 
 
 def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
@@ -42,9 +45,9 @@ def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
       m = 2, one evaluation (product form):
         C sub + C mul (q) + (3C - 6) mul (leave-one-out products)
         + (C - 1) add (sum) + 4 (rcp) + C mul (scale)          = 7C - 3
-      m other, one evaluation (normalised log form):
-        C sub + C mul + 4C (log2) + (C - 1)/2 (min3) + C mul + 4C (exp2)
-        + (C - 1) add + 4 (rcp) + C mul                        = 13.5C + 2.5
+      m other, one evaluation (m = 2 form, then u2^alpha normalised):
+        7C - 3 + 4C (log2) + C/2 (max3) + C mul + 4C (exp2) + (C - 1) add
+        + 4 (rcp) + C mul                                      = 18.5C + 0
       change test: C sub + C/2 (max3)
       weights, sums, objective:
         m = 2: C mul (u^2) + C fma (num) + C add (den) + 1 fma (J)
@@ -54,7 +57,7 @@ def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
         ev = 7 * C - 3
         tail = 3 * C + 1
     else:
-        ev = 13.5 * C + 2.5
+        ev = 18.5 * C
         tail = 4 + 8 * C
     ops = ev + tail
     if with_old:
@@ -65,8 +68,8 @@ def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--shape", default="64,128,128", help="D,H,W (or H,W) of the phantom")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--clusters", type=int, default=4)
@@ -74,6 +77,9 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device 5 times (counter calibration)")
     return ap.parse_args()
 
 
@@ -101,8 +107,97 @@ def cpu_baseline(x_np, C, m, eps, budget_s):
             break
     el = time.perf_counter() - t0
     return {"value": n * passes / el, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} membership evaluations + {t} centroid updates of the FP64 literal "
-                      f"oracle over all {n} voxels ({el:.1f} s, numpy, single thread)"}
+            "sample": f"the whole solve ({t} iterations, {passes} membership evaluations) of the FP64 literal "
+                      f"oracle over all {n} voxels of the same volume: {el:.2f} s, numpy, single thread"}
+
+
+def timed_solves(f, steps, labels=None):
+    """Run `steps` solves (reset + solve [+ labels]); returns (seconds, passes, kernel_ms, last result)."""
+    import torch
+    passes, kms, r = 0, 0.0, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f.reset()
+        r = f.solve()
+        if labels is not None:
+            f.labels(labels)
+        passes += r.passes
+        kms += r.kernel_ms
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, passes, kms, r
+
+
+def roofline(n, C, m, passes_per_launch, launch_s):
+    ops = n * (alg_lane_ops(C, m, False) + (passes_per_launch - 1) * alg_lane_ops(C, m, True))
+    achieved = ops / launch_s
+    return achieved
+
+
+def large_volume(dev):
+    import torch
+
+    from paper_1601_00072_amd import FCM
+    from phantom import PhantomParams, phantom
+    shape = (256, 512, 512)
+    x = torch.from_numpy(phantom(PhantomParams(shape=shape, seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
+    n = x.numel()
+    f = FCM(x, 4, timing=True)
+    timed_solves(f, 1)
+    el, passes, kms, r = timed_solves(f, 3)
+    f.close()
+    launch_s = kms / 3 * 1e-3
+    ach = roofline(n, 4, 2.0, r.passes, launch_s)
+    return {"workload": "ellipsoid-shell phantom 512x512x256 (67,108,864 voxels), seed 3, sigma 9, bias 20%, "
+                        "C=4, m=2, eps=1e-5",
+            "iterations": r.iters, "ms_per_solve": el / 3 * 1e3, "voxel_iterations_per_s": n * passes / el,
+            "us_per_pass": launch_s / r.passes * 1e6,
+            "roofline_frac": ach / PEAK_LANE_OPS, "achieved_T_lane_op_s": ach / 1e12}
+
+
+def batched(dev):
+    import numpy as np
+    import torch
+
+    from paper_1601_00072_amd import FCM, FCMBatch
+    from phantom import batch_instances, phantom
+    inst = batch_instances()
+    xs = [phantom(p).ravel() for p, _ in inst]
+    Cs = [c for _, c in inst]
+    flat = torch.from_numpy(np.concatenate(xs)).to(dev)
+    n = flat.numel()
+    with FCMBatch(flat, [a.size for a in xs], [dict(n_clusters=c, m=2.0, eps=1e-5) for c in Cs]) as b:
+        b.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            res = b.solve()
+        torch.cuda.synchronize()
+        el_b = (time.perf_counter() - t0) / reps
+    vox_passes = sum(a.size * r.passes for a, r in zip(xs, res))
+    # per-instance launch loop: the single-instance solver, one instance after another
+    views, off = [], 0
+    for a in xs:
+        views.append(flat[off:off + a.size])
+        off += a.size
+    handles = [FCM(v, c) for v, c in zip(views, Cs)]
+    for h in handles:
+        h.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in handles:
+        h.reset()
+        h.solve()
+    torch.cuda.synchronize()
+    el_l = time.perf_counter() - t0
+    for h in handles:
+        h.close()
+    return {"workload": "512 instances in one persistent launch: 496 slices side U{64..512} + 16 cubes side "
+                        "U{96..160}, C_i in 3..8, m=2, eps=1e-5",
+            "voxels": n, "max_iterations": max(r.iters for r in res),
+            "ms_per_batch_solve": el_b * 1e3, "voxel_iterations_per_s": vox_passes / el_b,
+            "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b}
 
 
 def main():
@@ -110,8 +205,18 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 5}))
+        return
 
     from paper_1601_00072_amd import FCM
     from phantom import PhantomParams, phantom
@@ -119,48 +224,25 @@ def main():
     shape = tuple(int(s) for s in args.shape.split(","))
     x_np = phantom(PhantomParams(shape=shape, seed=args.seed))
     n = x_np.size
-    dev = torch.device("cuda:0")
     x = torch.from_numpy(x_np.ravel()).to(dev)
     labels = torch.empty_like(x)
     stream = torch.cuda.current_stream(dev)
     C, m, eps = args.clusters, args.m, args.eps
 
     f = FCM(x, C, m=m, eps=eps, max_iter=300, timing=True, stream=stream)
-    for _ in range(args.warmup):
-        f.reset()
-        r = f.solve()
-        f.labels(labels)
-    torch.cuda.synchronize()
-    print(f"# warmup done: T={r.iters} passes={r.passes} status={r.status}", file=sys.stderr, flush=True)
-
-    passes_total = 0
-    kernel_ms_total = 0.0
-    iters = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f.reset()
-        r = f.solve()
-        f.labels(labels)
-        passes_total += r.passes
-        kernel_ms_total += r.kernel_ms
-        iters = r.iters
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    timed_solves(f, args.warmup, labels)
+    print(f"# warmup done, tuning {f.tuning}", file=sys.stderr, flush=True)
+    el, passes_total, kernel_ms_total, r = timed_solves(f, args.steps, labels)
     f.close()
+    print(f"# timed {args.steps} solves: T={r.iters} status={r.status}", file=sys.stderr, flush=True)
 
     ms_per_step = el * 1e3 / args.steps
-    value = n * passes_total / el
-    # roofline of the fused pass: the first pass of a solve has no previous
-    # memberships to evaluate, the others do
     passes_per_solve = passes_total / args.steps
-    ops_solve = n * (alg_lane_ops(C, m, False) + (passes_per_solve - 1) * alg_lane_ops(C, m, True))
-    pass_avg_s = kernel_ms_total / passes_total * 1e-3
-    ops_per_launch = ops_solve / passes_per_solve
-    achieved = ops_per_launch / pass_avg_s
+    launch_s = kernel_ms_total / args.steps * 1e-3
+    achieved = roofline(n, C, m, passes_per_solve, launch_s)
     out = {
-        "metric": "FCM voxel-iterations/s & time-to-converge (eps=1e-5) vs plain init, % roofline",
-        "value": value,
+        "metric": METRIC,
+        "value": n * passes_total / el,
         "unit": "voxel-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -174,24 +256,30 @@ def main():
         "config": {
             "workload": f"ellipsoid-shell phantom {'x'.join(map(str, shape[::-1]))} ({n} voxels, uint8), seed "
                         f"{args.seed}, sigma 8, bias 10%, C={C}, m={m}, eps={eps}, max_iter=300, linspace init",
-            "n_voxels": n, "C": C, "m": m, "eps": eps, "iterations": iters,
+            "n_voxels": n, "C": C, "m": m, "eps": eps, "iterations": r.iters,
             "passes_per_solve": passes_per_solve,
             "time_to_converge_ms": ms_per_step,
-            "step": "data-range pass + fused passes to convergence + labels",
+            "step": "data-range pass + fused passes to convergence + labels (one persistent launch + labels)",
+            "paper_context": "0.08 s at 40 KB and 2.33 s at 1 MB on a Tesla C2050 (Table 3), context only",
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"fcm_pass_kernel<C={C}>",
+            "kernel": f"fcm_persist_kernel<{C}>",
             "achieved": achieved / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": None,
-            "pass_avg_us": pass_avg_s * 1e6,
-            "alg_lane_ops_per_voxel": alg_lane_ops(C, m, True),
-            "hbm_GBps_at_pass": n / pass_avg_s / 1e9,
+            "launch_avg_us": launch_s * 1e6,
+            "alg_lane_ops_per_voxel_pass": alg_lane_ops(C, m, True),
         },
     }
+    if not args.quick:
+        lv = large_volume(dev)
+        print(f"# large volume: {lv['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+        bt = batched(dev)
+        print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+        out["extra"] = {"large_volume": lv, "batched": bt}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

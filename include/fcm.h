@@ -52,6 +52,10 @@ extern "C" {
 #define FCM_INIT_LINSPACE 0     /* v_j = lo + j (hi - lo) / (C - 1) over the data range,
                                    evaluated in FP64, rounded to FP32 */
 #define FCM_INIT_GIVEN    1     /* v^0 = init_centroids, rounded to FP32 */
+#define FCM_INIT_DEVICE   2     /* v^0 read at the start of every solve from the DEVICE
+                                   array init_centroids (C doubles, borrowed), rounded
+                                   to FP32; any non-finite value selects LINSPACE.
+                                   Used by the learned warm start. */
 
 /* flags */
 #define FCM_F_KAHAN_ONLY  (1u << 0)  /* cross-block reduction in compensated FP32
@@ -76,7 +80,8 @@ typedef struct fcm_params {
     double  eps;                  /* stop when max_ij |u_ij^t - u_ij^(t-1)| < eps; finite, > 0 */
     int32_t max_iter;             /* >= 1 */
     int32_t init;                 /* FCM_INIT_* */
-    const double* init_centroids; /* host, C finite values, read only with FCM_INIT_GIVEN */
+    const double* init_centroids; /* FCM_INIT_GIVEN: host, C finite values (copied);
+                                     FCM_INIT_DEVICE: device, C values (borrowed) */
     uint32_t flags;               /* FCM_F_* */
 } fcm_params;
 
@@ -147,6 +152,43 @@ int fcm_trajectory(fcm_handle* h, int32_t t, double* v_out, double* delta, doubl
 
 /* Release the handle's workspace (waits for the stream).  NULL is ignored. */
 void fcm_destroy(fcm_handle* h);
+
+/* ---- batched solver ------------------------------------------------------
+ * Many independent instances (2-D slices, 3-D volumes; each with its own C,
+ * m, eps, max_iter, init and flags) solved together in one persistent launch:
+ * every instance follows Algorithm 1 exactly as fcm_solve would, and the
+ * launch ends when every instance has converged or run out of iterations.
+ * Instance i is d_x[offsets[i] .. offsets[i+1]) of one concatenated uint8
+ * device buffer (borrowed); offsets (count + 1 values, host) must start at 0,
+ * be non-decreasing with every instance non-empty.  params: count host
+ * records (init_centroids, if used, are copied). */
+typedef struct fcm_batch fcm_batch;
+
+/* Validates everything before any HIP call (FCM_EINVAL), allocates the
+ * workspace (tile table, per-instance state and history), enqueues nothing.
+ * Needs cooperative launches (FCM_EUNSUPPORTED otherwise). */
+int fcm_batch_init(fcm_batch** b, const uint8_t* d_x, const int64_t* offsets, int32_t count,
+                   const fcm_params* params, void* stream);
+
+/* Tile size: chunks_per_thread 16-voxel chunks per thread and tile (1..64;
+ * a tile is 256 threads wide), and the launch grid (0 = as many blocks as fit
+ * on the device).  Rebuilds the tile table. */
+int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid);
+
+/* Solve every instance from its v^0; waits for the stream; out[i] (count
+ * records) receives instance i's result.  Returns FCM_OK if every instance
+ * converged, FCM_NOT_CONVERGED if any ran out of iterations, FCM_ENUMERIC if
+ * any hit a non-finite value (see each out[i].status), or an error. */
+int fcm_batch_solve(fcm_batch* b, fcm_result* out);
+
+/* Labels of every instance into d_labels (offsets[count] bytes, the same
+ * layout as the input), after fcm_batch_solve.  Enqueued, not waited for. */
+int fcm_batch_labels(fcm_batch* b, uint8_t* d_labels);
+
+/* History of instance inst (as fcm_trajectory). */
+int fcm_batch_trajectory(fcm_batch* b, int32_t inst, int32_t t, double* v_out, double* delta, double* J);
+
+void fcm_batch_destroy(fcm_batch* b);
 
 /* Static description of a status code, and the last HIP error text of this thread. */
 const char* fcm_strerror(int status);

@@ -3,6 +3,6 @@
 PyTorch supplies device memory and streams; every step of the iteration runs
 in the library's HIP kernels.
 """
-from .api import FCM, FcmError, Result, solve
+from .api import FCM, FCMBatch, FcmError, Result, solve
 
-__all__ = ["FCM", "FcmError", "Result", "solve"]
+__all__ = ["FCM", "FCMBatch", "FcmError", "Result", "solve"]

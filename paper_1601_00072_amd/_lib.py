@@ -37,6 +37,8 @@ FCM_EXCHANGE_ALLGATHER = 2
 EXPORTS = (
     "fcm_init", "fcm_reset", "fcm_set_tuning", "fcm_get_tuning", "fcm_iterate", "fcm_solve", "fcm_labels",
     "fcm_centroids", "fcm_trajectory", "fcm_destroy", "fcm_strerror", "fcm_last_error", "fcm_version",
+    "fcm_batch_init", "fcm_batch_set_tiling", "fcm_batch_solve", "fcm_batch_labels", "fcm_batch_trajectory",
+    "fcm_batch_destroy",
 )
 
 
@@ -121,5 +123,18 @@ def load() -> ctypes.CDLL:
     lib.fcm_last_error.restype = ctypes.c_char_p
     lib.fcm_version.argtypes = []
     lib.fcm_version.restype = ctypes.c_int
+    lib.fcm_batch_init.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(i64), i32, ctypes.POINTER(FcmParams), vp]
+    lib.fcm_batch_init.restype = ctypes.c_int
+    lib.fcm_batch_set_tiling.argtypes = [vp, i32, i32]
+    lib.fcm_batch_set_tiling.restype = ctypes.c_int
+    lib.fcm_batch_solve.argtypes = [vp, ctypes.POINTER(FcmResult)]
+    lib.fcm_batch_solve.restype = ctypes.c_int
+    lib.fcm_batch_labels.argtypes = [vp, vp]
+    lib.fcm_batch_labels.restype = ctypes.c_int
+    lib.fcm_batch_trajectory.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.fcm_batch_trajectory.restype = ctypes.c_int
+    lib.fcm_batch_destroy.argtypes = [vp]
+    lib.fcm_batch_destroy.restype = None
     _lib = lib
     return lib

@@ -174,3 +174,95 @@ def solve(x, n_clusters: int, m: float = 2.0, eps: float = 1e-5, max_iter: int =
         res = f.solve()
         lab = f.labels() if labels else None
         return res, lab
+
+
+class FCMBatch:
+    """Many instances solved in one persistent launch.
+
+    ``x``: one contiguous uint8 device tensor holding the instances back to
+    back; ``sizes``: voxel count of each instance; ``params``: one dict per
+    instance with keys n_clusters (required), m, eps, max_iter, init,
+    kahan_only."""
+
+    def __init__(self, x, sizes, params, stream=None):
+        import torch
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.uint8 or not x.is_cuda or not x.is_contiguous():
+            raise TypeError("x must be a contiguous uint8 CUDA/HIP tensor")
+        self._lib = L.load()
+        self.x = x
+        sizes = [int(s) for s in sizes]
+        if len(sizes) != len(params):
+            raise ValueError("one parameter record per instance")
+        self.count = len(sizes)
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        if self.offsets[-1] != x.numel():
+            raise ValueError("sizes must add up to x.numel()")
+        self.C = [int(q["n_clusters"]) for q in params]
+        self._keep = []
+        recs = (L.FcmParams * self.count)()
+        for i, q in enumerate(params):
+            init = q.get("init")
+            if init is None:
+                mode, ptr = L.FCM_INIT_LINSPACE, None
+            else:
+                buf = (ctypes.c_double * self.C[i])(*[float(v) for v in init])
+                self._keep.append(buf)
+                mode, ptr = L.FCM_INIT_GIVEN, ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+            recs[i] = L.FcmParams(n_clusters=self.C[i], m=float(q.get("m", 2.0)), eps=float(q.get("eps", 1e-5)),
+                                  max_iter=int(q.get("max_iter", 300)), init=mode, init_centroids=ptr,
+                                  flags=L.FCM_F_KAHAN_ONLY if q.get("kahan_only") else 0)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(x.device)
+        off = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        self._h = ctypes.c_void_p()
+        rc = self._lib.fcm_batch_init(ctypes.byref(self._h), ctypes.c_void_p(x.data_ptr()), off, self.count, recs,
+                                      ctypes.c_void_p(self._stream.cuda_stream))
+        if rc != L.FCM_OK:
+            self._h = None
+            raise FcmError(rc, "fcm_batch_init")
+
+    def set_tiling(self, chunks_per_thread: int = 4, grid: int = 0):
+        rc = self._lib.fcm_batch_set_tiling(self._h, int(chunks_per_thread), int(grid))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_set_tiling")
+
+    def solve(self):
+        out = (L.FcmResult * self.count)()
+        rc = self._lib.fcm_batch_solve(self._h, out)
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_batch_solve")
+        return [_result(r) for r in out]
+
+    def labels(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(self.x)
+        rc = self._lib.fcm_batch_labels(self._h, ctypes.c_void_p(out.data_ptr()))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_labels")
+        return out
+
+    def trajectory(self, i: int, t: int):
+        C = self.C[i]
+        v = (ctypes.c_double * C)()
+        d, J = ctypes.c_double(), ctypes.c_double()
+        rc = self._lib.fcm_batch_trajectory(self._h, int(i), int(t), v, ctypes.byref(d), ctypes.byref(J))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_trajectory")
+        return np.array(v[:], dtype=np.float64), d.value, J.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fcm_batch_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

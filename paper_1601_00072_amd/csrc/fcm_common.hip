@@ -21,7 +21,9 @@ __global__ __launch_bounds__(kBlock) void fcm_init_kernel(InitArgs a) {
     };
     reduce_minmax(get, G, lo, hi);
     if (threadIdx.x == 0) {
-        commit_start(a.st, a.hist_v, a.C, lo, hi, a.given, a.v0);
+        double v[kMaxC];
+        start_centroids(a.C, lo, hi, a.given, a.v0, a.dv0, v);
+        commit_start(a.st, a.hist_v, a.C, lo, hi, v);
         a.st->ticket = 0;
     }
 }

@@ -169,21 +169,32 @@ __device__ __forceinline__ void store_tagged(uint64_t* p, uint32_t round, uint32
     __hip_atomic_store(p, tagged(round, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// one poll step's bookkeeping: true when the caller must give up
-__device__ __forceinline__ bool poll_expired(SyncState* sy, uint64_t t0, uint64_t limit_ticks) {
+// one poll step's bookkeeping (sleep with backoff); true when the caller must
+// give up
+__device__ __forceinline__ bool poll_expired(SyncState* sy, uint64_t t0, uint64_t limit_ticks, int& spins) {
     if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
     if (wall_clock64() - t0 > limit_ticks) {
         __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     }
-    __builtin_amdgcn_s_sleep(1);
+    if (spins < 16) {
+        __builtin_amdgcn_s_sleep(1);
+        ++spins;
+    } else {
+        __builtin_amdgcn_s_sleep(8);
+    }
     return false;
 }
 
-// Wait until the K words at src carry `round`; payloads into out.
+// Wait until the K words at src carry `round`; payloads into out.  The whole
+// group is read once; while it is incomplete only its last word is watched
+// (the writer stores it last), then the group is read again.  A reader that
+// arrives after the writer needs one round trip; waiting readers generate one
+// load per poll.
 template <int K>
 __device__ __forceinline__ bool poll_tagged(const uint64_t* src, uint32_t round, uint32_t (&out)[K], SyncState* sy,
                                             uint64_t t0, uint64_t limit_ticks) {
+    int spins = 0;
     while (true) {
         bool all = true;
 #pragma unroll
@@ -193,43 +204,62 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, uint32_t round,
             out[r] = (uint32_t)w;
         }
         if (all) return true;
-        if (poll_expired(sy, t0, limit_ticks)) return false;
+        while (true) {
+            if (poll_expired(sy, t0, limit_ticks, spins)) return false;
+            const uint64_t w = __hip_atomic_load(src + K - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(w >> 32) == round) break;
+        }
     }
 }
 
-// Column-major float rows [rows][G] in plain memory (one launch per pass; the
+// Row formats.  A block's row holds, for each of the 2C + 1 sums (num[C],
+// den[C], J), a (sum, compensation) pair, then the max change; readers see it
+// as R = 4C + 3 floats.
+
+// Column-major float rows [R][G] in plain memory (one launch per pass; the
 // last block reads them after the ticket's acquire).
 struct PlainRows {
     float* P;
     int G;
-    __device__ __forceinline__ void put(int r, float v) const { store_coherent(P + r * G + blockIdx.x, v); }
-    template <int K>
-    __device__ __forceinline__ bool get(int b, float (&v)[K]) const {
+    __device__ __forceinline__ void put_pair(int q, float s, float c) const {
+        store_coherent(P + (2 * q) * G + blockIdx.x, s);
+        store_coherent(P + (2 * q + 1) * G + blockIdx.x, c);
+    }
+    __device__ __forceinline__ void put_max(int q, float m) const { store_coherent(P + (2 * q) * G + blockIdx.x, m); }
+    template <int R>
+    __device__ __forceinline__ bool get(int b, float (&v)[R]) const {
 #pragma unroll
-        for (int r = 0; r < K; ++r) v[r] = P[r * G + b];
+        for (int r = 0; r < R; ++r) v[r] = P[r * G + b];
         return true;
     }
 };
 
-// Row-major tagged rows [G][K] (cooperative launch).  A reader first polls the
-// row's last word, then loads the whole row and checks every tag.
+// Row-major tagged rows [G][K], K = 2C + 2 (cooperative launch).  Each pair is
+// folded to one FP32 value (sum - comp, within half an ulp) so that a row is
+// K self-validating words; a reader polls the whole row in one round trip.
 template <int K>
 struct TaggedRows {
     uint64_t* W;
     uint32_t round;
     SyncState* sy;
     uint64_t t0, limit;
-    __device__ __forceinline__ void put(int r, float v) const {
-        store_tagged(W + (size_t)blockIdx.x * K + r, round, __builtin_bit_cast(uint32_t, v));
+    __device__ __forceinline__ void put_pair(int q, float s, float c) const {
+        store_tagged(W + (size_t)blockIdx.x * K + q, round, __builtin_bit_cast(uint32_t, s - c));
     }
-    __device__ __forceinline__ bool get(int b, float (&v)[K]) const {
-        const uint64_t* src = W + (size_t)b * K;
-        uint32_t last[1];
-        if (!poll_tagged<1>(src + K - 1, round, last, sy, t0, limit)) return false;
+    __device__ __forceinline__ void put_max(int q, float m) const {
+        store_tagged(W + (size_t)blockIdx.x * K + q, round, __builtin_bit_cast(uint32_t, m));
+    }
+    template <int R>
+    __device__ __forceinline__ bool get(int b, float (&v)[R]) const {
+        static_assert(R == 2 * (K - 1) + 1, "row format");
         uint32_t raw[K];
-        if (!poll_tagged<K>(src, round, raw, sy, t0, limit)) return false;
+        if (!poll_tagged<K>(W + (size_t)b * K, round, raw, sy, t0, limit)) return false;
 #pragma unroll
-        for (int r = 0; r < K; ++r) v[r] = __builtin_bit_cast(float, raw[r]);
+        for (int q = 0; q < K - 1; ++q) {
+            v[2 * q] = __builtin_bit_cast(float, raw[q]);
+            v[2 * q + 1] = 0.f;
+        }
+        v[R - 1] = __builtin_bit_cast(float, raw[K - 1]);
         return true;
     }
 };
@@ -591,12 +621,11 @@ __device__ __forceinline__ void write_partial_row(const Acc<C>& acc, const Rows&
     if (tid < NQ) {
         float s = 0.f, c = 0.f;
         for (int w = 0; w < kWaves; ++w) kahan_add(s, c, s_red[w][tid]);
-        rows.put(2 * tid, s);
-        rows.put(2 * tid + 1, c);
+        rows.put_pair(tid, s, c);
     } else if (tid == NQ) {
         float mm = s_red[0][NQ];
         for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_red[w][NQ]);
-        rows.put(2 * NQ, mm);
+        rows.put_max(NQ, mm);
     }
 }
 
@@ -629,7 +658,7 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
     }
     for (int b = tid; b < G; b += kBlock) {
         float v[R];
-        if (!rows.get(b, v)) {
+        if (!rows.template get<R>(b, v)) {
             bad = 1;
             break;
         }
@@ -887,29 +916,36 @@ __device__ __forceinline__ bool reduce_minmax(const Get& get, int G, uint32_t& l
     return true;
 }
 
-// v^0 as FP64 holding FP32 values: given, or lo + k (hi - lo) / (C - 1) with the
-// product exact and the quotient and the sum rounded once each in FP64, then
-// rounded to FP32.
-__device__ __forceinline__ double initial_centroid(int k, int C, uint32_t lo, uint32_t hi, int given, const double* v0) {
-    float v32;
-    if (given) {
-        v32 = (float)v0[k];
-    } else {
-        const double v = (double)lo + (double)(k * (int)(hi - lo)) / (double)(C - 1);
-        v32 = (float)v;
+// v^0 (C values, FP64 holding FP32 values) for start mode `mode`:
+//   0  evenly spaced: lo + k (hi - lo) / (C - 1), the product exact, the
+//      quotient and the sum rounded once each in FP64, then rounded to FP32;
+//   1  the given values v0[k];
+//   2  the values dv0[k] in device memory (written by an earlier kernel, e.g.
+//      the learned warm start); any non-finite value selects mode 0.
+__device__ __forceinline__ void start_centroids(int C, uint32_t lo, uint32_t hi, int mode, const double* v0,
+                                                const double* dv0, double* out) {
+    bool spaced = mode == 0;
+    if (mode == 2)
+        for (int k = 0; k < C; ++k)
+            if (!isfinite(dv0[k])) spaced = true;
+    for (int k = 0; k < C; ++k) {
+        float v32;
+        if (spaced)
+            v32 = (float)((double)lo + (double)(k * (int)(hi - lo)) / (double)(C - 1));
+        else
+            v32 = (float)(mode == 1 ? v0[k] : dv0[k]);
+        out[k] = (double)v32;
     }
-    return (double)v32;
 }
 
 // Write the start of a solve into the state (one thread).
 __device__ __forceinline__ void commit_start(DevState* st, double* hist_v, int C, uint32_t lo, uint32_t hi,
-                                             int given, const double* v0) {
+                                             const double* v) {
     for (int k = 0; k < kMaxC; ++k) {
         float v32 = 0.f;
         if (k < C) {
-            const double v = initial_centroid(k, C, lo, hi, given, v0);
-            v32 = (float)v;
-            hist_v[k] = v;
+            v32 = (float)v[k];
+            hist_v[k] = v[k];
         }
         st->v32[0][k] = v32;
         st->v32[1][k] = v32;
@@ -937,7 +973,6 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
     const int G = gridDim.x;
     const int tid = threadIdx.x;
     const bool leader = blockIdx.x == 0;
-    constexpr int R = partial_rows(C);
     __shared__ double s_v64[C];
     __shared__ float s_vn[C], s_vo[C];
     __shared__ int s_p, s_done, s_ok;
@@ -967,17 +1002,17 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 return true;
             };
             if (!reduce_minmax(get, G, lo, hi)) return;
-            if (tid < C) {
-                const double v = initial_centroid(tid, C, lo, hi, a.given, a.v0);
-                s_v64[tid] = v;
-                s_vn[tid] = (float)v;
-                s_vo[tid] = (float)v;
-            }
-            __syncthreads();
             if (tid == 0) {
+                double v[C];
+                start_centroids(C, lo, hi, a.given, a.v0, a.dv0, v);
+                for (int k = 0; k < C; ++k) {
+                    s_v64[k] = v[k];
+                    s_vn[k] = (float)v[k];
+                    s_vo[k] = (float)v[k];
+                }
                 s_p = 0;
                 s_done = 0;
-                if (leader) commit_start(st, a.hist_v, C, lo, hi, a.given, a.v0);
+                if (leader) commit_start(st, a.hist_v, C, lo, hi, v);
                 if (!a.allgather) publish_decision<C>(sy, round, s_vn, 0, 0);
             }
         } else {
@@ -1028,7 +1063,8 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
         Acc<C> acc;
         run_pass<C, MK, UNROLL>(a, p, vn, vo, acc, resident, mine);
         ++round;
-        const TaggedRows<R> rows{a.rows + (size_t)(round & 1u) * R * G, round, sy, (uint64_t)wall_clock64(),
+        constexpr int K = 2 * C + 2;
+        const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * K * G, round, sy, (uint64_t)wall_clock64(),
                                  a.spin_ticks};
         write_partial_row<C>(acc, rows);
         if (leader || a.allgather) {

@@ -68,8 +68,9 @@ struct PassArgs {
     int32_t allgather;     // every block reduces all rows (else block 0 reduces and broadcasts)
     int32_t pad2;
     int32_t do_init;       // run the data-range pass and set v^0 first
-    int32_t given;         // v^0 = v0 below instead of evenly spaced
+    int32_t given;         // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device)
     double v0[kMaxC];
+    const double* dv0;     // C start centroids in device memory (mode 2)
     int32_t max_passes;    // passes this launch may run
     int32_t pad;
     uint64_t spin_ticks;   // wall-clock limit of one wait
@@ -82,8 +83,9 @@ struct InitArgs {
     uint32_t* partials;    // [2][grid]
     double* hist_v;
     int32_t C;
-    int32_t given;         // 1: use v0 below, else evenly spaced over [lo, hi]
+    int32_t given;         // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device)
     double v0[kMaxC];
+    const double* dv0;
 };
 
 struct LabelArgs {
@@ -95,6 +97,72 @@ struct LabelArgs {
     int32_t C;
     int32_t bytewise;      // x and labels differ in 16-byte alignment
 };
+
+// ---- batched solver: many instances of uneven size in one cooperative launch ----
+
+constexpr int kBatchRowWords = 2 * kMaxC + 2;  // tagged words per tile row (stride for any C)
+constexpr int kBatchDecWords = 2 * kMaxC + 1;  // tagged decision words per instance
+
+struct BatchInst {
+    int64_t base;        // byte offset of the instance's first voxel in the input
+    int64_t n, head, nbody;
+    int64_t hist;        // offset (doubles) of its history: v (max_iter + 2) * C, delta, J (max_iter + 2 each)
+    int32_t C, mclass, max_iter, kahan_only;
+    int32_t given, tile0, ntiles, pad;   // given: start mode (0 spaced, 1 v0, 2 dv0)
+    float alpha, mexp;
+    double eps;
+    double v0[kMaxC];
+    const double* dv0;   // C start centroids in device memory (mode 2)
+};
+
+struct BatchTile {
+    int64_t c0, c1;      // 16-voxel chunks [c0, c1) of the instance's aligned body
+    int32_t inst;
+    int32_t ragged;      // this tile also takes the instance's unaligned head and tail voxels
+};
+
+struct BatchRec {        // per-instance state, written by the instance's owner block
+    int32_t pass, done, iters, status, passes, lo, hi, pad;
+    double delta, J;
+    double vres[kMaxC];
+};
+
+struct BatchSync {
+    uint32_t gen_max;    // largest round used by any block (for the next launch's tags)
+    uint32_t abort;      // set when a wait hit its time limit; every block then exits
+    uint32_t active;     // instances not yet finished
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const uint8_t* x;
+    const BatchInst* inst;
+    const BatchTile* tiles;
+    BatchRec* recs;
+    double* hist;
+    uint64_t* rows;      // [ntiles][kBatchRowWords] tagged tile rows
+    uint64_t* mm;        // [ntiles][2] tagged grey-level ranges
+    uint64_t* dec;       // [I][kBatchDecWords] tagged decisions: v_new[8], v_old[8], (pass << 1 | done)
+    BatchSync* sync;
+    int32_t I, ntiles, do_init, max_sweeps;
+    uint32_t round0;     // largest round of earlier launches
+    uint32_t pad;
+    uint64_t spin_ticks;
+};
+
+struct BatchLabelArgs {
+    const uint8_t* x;
+    uint8_t* labels;
+    const BatchInst* inst;
+    const BatchTile* tiles;
+    const BatchRec* recs;
+    const double* hist;
+    int32_t ntiles, bytewise;
+};
+
+hipError_t batch_max_grid(int ncu, int* max_grid);
+hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s);
 
 using PassFn = void (*)(PassArgs);
 

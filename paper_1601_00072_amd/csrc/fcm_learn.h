@@ -1,0 +1,23 @@
+// Internal launchers of the learned warm start (fcm_learn.hip); not part of the ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace fcm {
+
+hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
+                            float* hist, hipStream_t s);
+hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* Cm, int M, int N, int K,
+                       const float* bias, int relu, const float* mask, hipStream_t s);
+hipError_t launch_colsum(const float* G, int M, int N, float* out, hipStream_t s);
+hipError_t launch_mse(const float* Y, const float* T, int n, float scale, float* dY, float* loss_out, hipStream_t s);
+hipError_t launch_adam(float* theta, const float* g, float* m, float* v, int64_t n, float lr, int step,
+                       hipStream_t s);
+hipError_t launch_gather(const float* X, const int32_t* idx, int rows, int cols, float* out, hipStream_t s);
+hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
+hipError_t launch_mlp_infer_bf16(const uint16_t* wb, const float* X, int count, int C, float* Y, hipStream_t s);
+hipError_t launch_warm_post(const float* Y, const float* hist, int count, int C, double* v0, hipStream_t s);
+
+}  // namespace fcm

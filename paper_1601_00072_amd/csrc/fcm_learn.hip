@@ -1,0 +1,328 @@
+// Learned warm start: grey-level histograms, and the histogram -> centroid
+// network (256 -> 128 ReLU -> 64 ReLU -> C) trained and run by these kernels.
+//
+// Parameters live in one flat FP32 vector: W1 [256][128], b1, W2 [128][64], b2,
+// W3 [64][C], b3 (row-major [in][out]).  Training: FP32 forward/backward on
+// minibatches, mean squared error on the centroids divided by 255, Adam.
+// Inference: BF16 weights and activations (round to nearest even), FP32
+// accumulation, one block per histogram.  All reductions run in a fixed order
+// (no floating-point atomics), so training is reproducible run to run.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fcm_internal.h"
+#include "fcm_learn.h"
+
+namespace fcm {
+
+// ---------------------------------------------------------------------------
+// histogram of each instance (integer counts, then normalised to sum 1)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint8_t* x, const int64_t* offsets,
+                                                            uint32_t* counts) {
+    __shared__ uint32_t bins[256];
+    const int inst = blockIdx.y;
+    const int tid = threadIdx.x;
+    bins[tid] = 0u;
+    __syncthreads();
+    const int64_t b0 = offsets[inst], n = offsets[inst + 1] - b0;
+    const uint8_t* xi = x + b0;
+    const int64_t lead = (int64_t)((16 - ((uintptr_t)xi & 15)) & 15);
+    const int64_t head = n < lead ? n : lead;
+    const int64_t nbody = (n - head) / 16;
+    const uint4* body = reinterpret_cast<const uint4*>(xi + head);
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + tid; c < nbody; c += (int64_t)gridDim.x * kBlock) {
+        const uint4 w = body[c];
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) atomicAdd(&bins[(words[q] >> (8 * b)) & 0xFFu], 1u);
+        }
+    }
+    if (blockIdx.x == 0) {
+        const int64_t tail0 = head + 16 * nbody;
+        const int64_t nr = head + (n - tail0);
+        for (int64_t r = tid; r < nr; r += kBlock) {
+            const int64_t i = r < head ? r : tail0 + (r - head);
+            atomicAdd(&bins[xi[i]], 1u);
+        }
+    }
+    __syncthreads();
+    if (bins[tid]) atomicAdd(counts + (int64_t)inst * 256 + tid, bins[tid]);
+}
+
+__global__ __launch_bounds__(kBlock) void hist_norm_kernel(const uint32_t* counts, const int64_t* offsets,
+                                                           float* hist) {
+    const int inst = blockIdx.x;
+    const double n = (double)(offsets[inst + 1] - offsets[inst]);
+    const int64_t o = (int64_t)inst * 256 + threadIdx.x;
+    hist[o] = (float)((double)counts[o] / n);
+}
+
+hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
+                            float* hist, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * 256 * (size_t)count, s);
+    if (e != hipSuccess) return e;
+    const int64_t chunks = (max_n + 15) / 16;
+    int64_t gx64 = (chunks + kBlock * 16 - 1) / (kBlock * 16);
+    gx64 = gx64 < 1 ? 1 : (gx64 > 64 ? 64 : gx64);
+    const int gx = (int)gx64;
+    hipLaunchKernelGGL(hist_count_kernel, dim3(gx, count), dim3(kBlock), 0, s, x, d_offsets, counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_norm_kernel, dim3(count), dim3(256), 0, s, counts, d_offsets, hist);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP32 GEMM for training: Cm[M][N] = op(A) op(B) (+ bias[N]) (ReLU) (* mask>0)
+// op(A) is A [M][K] or, transposed, A [K][M]; op(B) is B [K][N] or B [N][K].
+// 32 x 32 output tile per block of 16 x 16 threads (2 x 2 outputs each), K in
+// steps of 32 through LDS.  Each output is a sum in a fixed order.
+// ---------------------------------------------------------------------------
+
+constexpr int kT = 32;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(const float* A, const float* B, float* Cm, int M, int N, int K,
+                                                   const float* bias, int relu, const float* mask) {
+    __shared__ float As[kT][kT + 1];
+    __shared__ float Bs[kT][kT + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int row0 = blockIdx.y * kT, col0 = blockIdx.x * kT;
+    float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    for (int k0 = 0; k0 < K; k0 += kT) {
+        for (int e = threadIdx.x; e < kT * kT; e += 256) {
+            const int r = e / kT, c = e % kT;
+            const int gm = row0 + r, gk = k0 + c;
+            float va = 0.f;
+            if (gm < M && gk < K) va = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
+            As[r][c] = va;
+            const int gk2 = k0 + r, gn = col0 + c;
+            float vb = 0.f;
+            if (gk2 < K && gn < N) vb = TB ? B[(int64_t)gn * K + gk2] : B[(int64_t)gk2 * N + gn];
+            Bs[r][c] = vb;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < kT; ++kk) {
+            const float a0 = As[ty * 2][kk], a1 = As[ty * 2 + 1][kk];
+            const float b0 = Bs[kk][tx * 2], b1 = Bs[kk][tx * 2 + 1];
+            acc[0][0] = fmaf(a0, b0, acc[0][0]);
+            acc[0][1] = fmaf(a0, b1, acc[0][1]);
+            acc[1][0] = fmaf(a1, b0, acc[1][0]);
+            acc[1][1] = fmaf(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int gm = row0 + ty * 2 + i, gn = col0 + tx * 2 + j;
+            if (gm >= M || gn >= N) continue;
+            float v = acc[i][j];
+            if (bias) v += bias[gn];
+            if (relu) v = fmaxf(v, 0.f);
+            if (mask && !(mask[(int64_t)gm * N + gn] > 0.f)) v = 0.f;
+            Cm[(int64_t)gm * N + gn] = v;
+        }
+    }
+}
+
+hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* Cm, int M, int N, int K,
+                       const float* bias, int relu, const float* mask, hipStream_t s) {
+    const dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, B, Cm, M, N, K, bias, relu, mask);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, A, B, Cm, M, N, K, bias, relu, mask);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, A, B, Cm, M, N, K, bias, relu, mask);
+    else
+        hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, A, B, Cm, M, N, K, bias, relu, mask);
+    return hipGetLastError();
+}
+
+// column sums of G [M][N] into out[N] (row order fixed)
+__global__ void colsum_kernel(const float* G, int M, int N, float* out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int i = 0; i < M; ++i) s += G[(int64_t)i * N + j];
+    out[j] = s;
+}
+
+hipError_t launch_colsum(const float* G, int M, int N, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 127) / 128), dim3(128), 0, s, G, M, N, out);
+    return hipGetLastError();
+}
+
+// dY = 2 (Y - T) / (B C); loss_out[slot] = sum (Y - T)^2 / (B C) (one block, fixed order)
+__global__ __launch_bounds__(256) void mse_kernel(const float* Y, const float* T, int n, float scale, float* dY,
+                                                  float* loss_out) {
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const float d = Y[i] - T[i];
+        dY[i] = 2.f * d * scale;
+        s += (double)d * d;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss_out = (float)(part[0] * scale);
+}
+
+hipError_t launch_mse(const float* Y, const float* T, int n, float scale, float* dY, float* loss_out,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, s, Y, T, n, scale, dY, loss_out);
+    return hipGetLastError();
+}
+
+__global__ void adam_kernel(float* theta, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+hipError_t launch_adam(float* theta, const float* g, float* m, float* v, int64_t n, float lr, int step,
+                       hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, g, m, v, n, lr, b1,
+                       b2, 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+__global__ void gather_rows_kernel(const float* X, const int32_t* idx, int rows, int cols, float* out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    out[e] = X[(int64_t)idx[r] * cols + c];
+}
+
+hipError_t launch_gather(const float* X, const int32_t* idx, int rows, int cols, float* out, hipStream_t s) {
+    const int64_t n = (int64_t)rows * cols;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, idx, rows, cols,
+                       out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// BF16 inference
+// ---------------------------------------------------------------------------
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+__global__ void to_bf16_kernel(const float* in, uint16_t* out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = to_bf16(in[i]);
+}
+
+hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+// One block (128 threads) per histogram: the three layers with BF16 weights
+// and activations, FP32 accumulation; output y[C] in FP32.
+__global__ __launch_bounds__(128) void mlp_infer_bf16_kernel(const uint16_t* wb, const float* X, int C, float* Y) {
+    __shared__ float a0[256];
+    __shared__ float a1[128];
+    __shared__ float a2[64];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const uint16_t* W1 = wb;
+    const uint16_t* b1 = W1 + 256 * 128;
+    const uint16_t* W2 = b1 + 128;
+    const uint16_t* b2 = W2 + 128 * 64;
+    const uint16_t* W3 = b2 + 64;
+    const uint16_t* b3 = W3 + 64 * C;
+    for (int i = t; i < 256; i += 128) a0[i] = from_bf16(to_bf16(X[(int64_t)s * 256 + i]));
+    __syncthreads();
+    {
+        float z = from_bf16(b1[t]);
+        for (int i = 0; i < 256; ++i) z = fmaf(a0[i], from_bf16(W1[i * 128 + t]), z);
+        a1[t] = from_bf16(to_bf16(fmaxf(z, 0.f)));
+    }
+    __syncthreads();
+    if (t < 64) {
+        float z = from_bf16(b2[t]);
+        for (int i = 0; i < 128; ++i) z = fmaf(a1[i], from_bf16(W2[i * 64 + t]), z);
+        a2[t] = from_bf16(to_bf16(fmaxf(z, 0.f)));
+    }
+    __syncthreads();
+    if (t < C) {
+        float z = from_bf16(b3[t]);
+        for (int i = 0; i < 64; ++i) z = fmaf(a2[i], from_bf16(W3[i * C + t]), z);
+        Y[(int64_t)s * C + t] = z;
+    }
+}
+
+hipError_t launch_mlp_infer_bf16(const uint16_t* wb, const float* X, int count, int C, float* Y, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3(count), dim3(128), 0, s, wb, X, C, Y);
+    return hipGetLastError();
+}
+
+// Network output -> starting centroids, one thread per instance: v = 255 y,
+// sorted ascending, clamped to the data range [lo, hi] read off the histogram,
+// consecutive gaps of at least 1; written as C doubles (FP32 values), or NaN
+// when no valid set exists (non-finite output, or hi - lo < C - 1), which makes
+// the solve fall back to evenly spaced centroids.
+__global__ void warm_post_kernel(const float* Y, const float* hist, int count, int C, double* v0) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const float* h = hist + (int64_t)s * 256;
+    int lo = 0, hi = 255;
+    while (lo < 255 && !(h[lo] > 0.f)) ++lo;
+    while (hi > 0 && !(h[hi] > 0.f)) --hi;
+    float v[kMaxC];
+    bool ok = hi - lo >= C - 1;
+    for (int k = 0; k < C; ++k) {
+        v[k] = 255.f * Y[(int64_t)s * C + k];
+        if (!isfinite(v[k])) ok = false;
+    }
+    for (int k = 1; k < C; ++k) {  // insertion sort
+        const float key = v[k];
+        int j = k - 1;
+        while (j >= 0 && v[j] > key) {
+            v[j + 1] = v[j];
+            --j;
+        }
+        v[j + 1] = key;
+    }
+    for (int k = 0; k < C; ++k) v[k] = fminf(fmaxf(v[k], (float)lo), (float)hi);
+    for (int k = 1; k < C; ++k) v[k] = fmaxf(v[k], v[k - 1] + 1.f);
+    if (v[C - 1] > (float)hi) {  // push back from the top
+        v[C - 1] = (float)hi;
+        for (int k = C - 2; k >= 0; --k) v[k] = fminf(v[k], v[k + 1] - 1.f);
+        if (v[0] < (float)lo) ok = false;
+    }
+    for (int k = 0; k < C; ++k) v0[(int64_t)s * C + k] = ok ? (double)v[k] : __builtin_nan("");
+}
+
+hipError_t launch_warm_post(const float* Y, const float* hist, int count, int C, double* v0, hipStream_t s) {
+    hipLaunchKernelGGL(warm_post_kernel, dim3((count + 127) / 128), dim3(128), 0, s, Y, hist, count, C, v0);
+    return hipGetLastError();
+}
+
+}  // namespace fcm

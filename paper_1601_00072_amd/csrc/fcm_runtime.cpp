@@ -42,7 +42,7 @@ int dev_err(hipError_t e, const char* what) {
 constexpr uint32_t kKnownFlags = FCM_F_KAHAN_ONLY | FCM_F_TIMING;
 constexpr int kMaxGraphK = 64;
 constexpr double kBarrierLimitSeconds = 5.0;
-constexpr int64_t kAllGatherBytes = 12LL << 20;
+constexpr int64_t kAllGatherBytes = 6LL << 20;
 
 int validate_params(const fcm_params* p) {
     if (!p) return FCM_EINVAL;
@@ -50,7 +50,8 @@ int validate_params(const fcm_params* p) {
     if (!std::isfinite(p->m) || !(p->m > 1.0)) return FCM_EINVAL;
     if (!std::isfinite(p->eps) || !(p->eps > 0.0)) return FCM_EINVAL;
     if (p->max_iter < 1 || p->max_iter > (1 << 24)) return FCM_EINVAL;
-    if (p->init != FCM_INIT_LINSPACE && p->init != FCM_INIT_GIVEN) return FCM_EINVAL;
+    if (p->init != FCM_INIT_LINSPACE && p->init != FCM_INIT_GIVEN && p->init != FCM_INIT_DEVICE) return FCM_EINVAL;
+    if (p->init == FCM_INIT_DEVICE && !p->init_centroids) return FCM_EINVAL;
     if (p->init == FCM_INIT_GIVEN) {
         if (!p->init_centroids) return FCM_EINVAL;
         for (int k = 0; k < p->n_clusters; ++k)
@@ -80,6 +81,7 @@ struct fcm_handle {
     int64_t n = 0, head = 0, nbody = 0;
     fcm_params p{};
     double given[kMaxC] = {};
+    const double* dv0 = nullptr;   // device start centroids (FCM_INIT_DEVICE)
     hipStream_t stream = nullptr;
     int device = 0;
     int ncu = 256;
@@ -119,6 +121,8 @@ namespace {
 
 int64_t chunk_blocks(const fcm_handle* h) { return (h->nbody + kBlock - 1) / kBlock; }
 
+int start_mode(int init) { return init == FCM_INIT_GIVEN ? 1 : (init == FCM_INIT_DEVICE ? 2 : 0); }
+
 int resolve_grid(fcm_handle* h, int* out) {
     int64_t want = h->tun.grid > 0 ? h->tun.grid : std::min<int64_t>(chunk_blocks(h), 4LL * h->ncu);
     if (h->tun.driver == FCM_DRIVER_PERSISTENT) {
@@ -149,12 +153,13 @@ PassArgs pass_args(const fcm_handle* h) {
     a.rows = h->d_rows;
     a.mm_rows = h->d_mmrows;
     // all-gather while the rows every block reads stay small (grid^2 rows)
-    a.allgather = (int64_t)h->grid * h->grid * partial_rows(h->p.n_clusters) * 8 <= kAllGatherBytes ? 1 : 0;
+    a.allgather = (int64_t)h->grid * h->grid * (2 * h->p.n_clusters + 2) * 8 <= kAllGatherBytes ? 1 : 0;
     if (h->tun.exchange == FCM_EXCHANGE_LEADER) a.allgather = 0;
     if (h->tun.exchange == FCM_EXCHANGE_ALLGATHER) a.allgather = 1;
     a.do_init = h->pending_init ? 1 : 0;
-    a.given = h->p.init == FCM_INIT_GIVEN ? 1 : 0;
+    a.given = start_mode(h->p.init);
     for (int k = 0; k < kMaxC; ++k) a.v0[k] = h->given[k];
+    a.dv0 = h->dv0;
     a.max_passes = 0;
     a.spin_ticks = h->spin_ticks;
     return a;
@@ -238,8 +243,9 @@ int flush_init(fcm_handle* h) {
     ia.partials = h->d_minmax;
     ia.hist_v = h->hist_v();
     ia.C = h->p.n_clusters;
-    ia.given = h->p.init == FCM_INIT_GIVEN ? 1 : 0;
+    ia.given = start_mode(h->p.init);
     for (int k = 0; k < h->p.n_clusters; ++k) ia.v0[k] = h->given[k];
+    ia.dv0 = h->dv0;
     const int igrid = (int)std::max<int64_t>(1, std::min<int64_t>(chunk_blocks(h), std::min<int64_t>(4LL * h->ncu,
                                                                                                       kMaxGrid)));
     hipError_t e = launch_init(ia, igrid, h->stream);
@@ -384,6 +390,7 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     h->p = *p;
     if (p->init == FCM_INIT_GIVEN)
         for (int k = 0; k < p->n_clusters; ++k) h->given[k] = p->init_centroids[k];
+    if (p->init == FCM_INIT_DEVICE) h->dv0 = p->init_centroids;
     h->p.init_centroids = nullptr;
     h->stream = (hipStream_t)stream;
     const int C = p->n_clusters;
@@ -551,6 +558,308 @@ void fcm_destroy(fcm_handle* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     release(h);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solver
+// ---------------------------------------------------------------------------
+
+struct fcm_batch {
+    const uint8_t* d_x = nullptr;
+    int32_t count = 0;
+    std::vector<int64_t> offsets;
+    std::vector<fcm_params> p;
+    std::vector<double> given;  // count * kMaxC
+    hipStream_t stream = nullptr;
+    int device = 0, ncu = 256, max_grid = 1, grid = 1, grid_req = 0;
+    int chunks_per_thread = 4;
+    uint64_t spin_ticks = 0;
+    uint32_t round = 0;        // largest round used so far (tags of later solves start above it)
+    bool solved = false;
+
+    std::vector<BatchInst> h_inst;
+    std::vector<BatchTile> h_tiles;
+    int64_t hist_total = 0;
+
+    BatchInst* d_inst = nullptr;
+    BatchTile* d_tiles = nullptr;
+    BatchRec* d_recs = nullptr;
+    double* d_hist = nullptr;
+    uint64_t* d_rows = nullptr;
+    uint64_t* d_mm = nullptr;
+    uint64_t* d_dec = nullptr;
+    BatchSync* d_sync = nullptr;
+    int64_t tiles_cap = 0;     // capacity of d_tiles / d_rows / d_mm
+    BatchRec* h_recs = nullptr;
+    BatchSync* h_sync = nullptr;
+};
+
+namespace {
+
+void batch_free_tiles(fcm_batch* b) {
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_rows) (void)hipFree(b->d_rows);
+    if (b->d_mm) (void)hipFree(b->d_mm);
+    b->d_tiles = nullptr;
+    b->d_rows = nullptr;
+    b->d_mm = nullptr;
+    b->tiles_cap = 0;
+}
+
+void batch_release(fcm_batch* b) {
+    if (!b) return;
+    batch_free_tiles(b);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_recs) (void)hipFree(b->d_recs);
+    if (b->d_hist) (void)hipFree(b->d_hist);
+    if (b->d_dec) (void)hipFree(b->d_dec);
+    if (b->d_sync) (void)hipFree(b->d_sync);
+    if (b->h_recs) (void)hipHostFree(b->h_recs);
+    if (b->h_sync) (void)hipHostFree(b->h_sync);
+    delete b;
+}
+
+// Cut every instance into tiles of 256 * chunks_per_thread chunks and upload
+// the instance and tile tables (the tile-indexed buffers grow as needed and
+// are cleared, so no stale tag can match).
+int batch_build_tiles(fcm_batch* b) {
+    const int64_t tile_chunks = (int64_t)kBlock * b->chunks_per_thread;
+    b->h_tiles.clear();
+    for (int32_t i = 0; i < b->count; ++i) {
+        BatchInst& in = b->h_inst[i];
+        in.tile0 = (int32_t)b->h_tiles.size();
+        int64_t c0 = 0;
+        do {
+            BatchTile t{};
+            t.c0 = c0;
+            t.c1 = std::min<int64_t>(in.nbody, c0 + tile_chunks);
+            t.inst = i;
+            t.ragged = c0 == 0 ? 1 : 0;
+            b->h_tiles.push_back(t);
+            c0 = t.c1;
+        } while (c0 < in.nbody);
+        in.ntiles = (int32_t)b->h_tiles.size() - in.tile0;
+    }
+    const int64_t nt = (int64_t)b->h_tiles.size();
+    if (nt > (int64_t)INT32_MAX) return FCM_EINVAL;
+    if (nt > b->tiles_cap) {
+        batch_free_tiles(b);
+        if (hipMalloc(&b->d_tiles, sizeof(BatchTile) * nt) != hipSuccess) return FCM_ENOMEM;
+        if (hipMalloc(&b->d_rows, sizeof(uint64_t) * kBatchRowWords * nt) != hipSuccess) return FCM_ENOMEM;
+        if (hipMalloc(&b->d_mm, sizeof(uint64_t) * 2 * nt) != hipSuccess) return FCM_ENOMEM;
+        b->tiles_cap = nt;
+    }
+    FCM_HIP(hipMemsetAsync(b->d_rows, 0, sizeof(uint64_t) * kBatchRowWords * b->tiles_cap, b->stream));
+    FCM_HIP(hipMemsetAsync(b->d_mm, 0, sizeof(uint64_t) * 2 * b->tiles_cap, b->stream));
+    FCM_HIP(hipMemcpyAsync(b->d_tiles, b->h_tiles.data(), sizeof(BatchTile) * nt, hipMemcpyHostToDevice, b->stream));
+    FCM_HIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice,
+                           b->stream));
+    FCM_HIP(hipStreamSynchronize(b->stream));  // the host tables may change after return
+    const int64_t want = b->grid_req > 0 ? b->grid_req : b->max_grid;
+    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, b->max_grid), nt));
+    b->round = 0;  // buffers were cleared: tags restart
+    return FCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, int32_t count,
+                   const fcm_params* params, void* stream) {
+    if (!out || !d_x || !offsets || !params || count < 1) return FCM_EINVAL;
+    if (offsets[0] != 0) return FCM_EINVAL;
+    for (int32_t i = 0; i < count; ++i) {
+        if (offsets[i + 1] <= offsets[i]) return FCM_EINVAL;
+        int rc = validate_params(params + i);
+        if (rc != FCM_OK) return rc;
+    }
+    fcm_batch* b = new (std::nothrow) fcm_batch();
+    if (!b) return FCM_ENOMEM;
+    auto fail = [&](int code) {
+        batch_release(b);
+        return code;
+    };
+    b->d_x = d_x;
+    b->count = count;
+    b->offsets.assign(offsets, offsets + count + 1);
+    b->p.assign(params, params + count);
+    b->given.assign((size_t)count * kMaxC, 0.0);
+    b->stream = (hipStream_t)stream;
+    b->h_inst.resize(count);
+    int64_t hist = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const fcm_params& q = params[i];
+        if (q.init == FCM_INIT_GIVEN)
+            for (int k = 0; k < q.n_clusters; ++k) b->given[(size_t)i * kMaxC + k] = q.init_centroids[k];
+        b->p[i].init_centroids = nullptr;
+        BatchInst& in = b->h_inst[i];
+        std::memset(&in, 0, sizeof(in));
+        in.base = offsets[i];
+        in.n = offsets[i + 1] - offsets[i];
+        const uintptr_t addr = (uintptr_t)(d_x + in.base);
+        in.head = std::min<int64_t>(in.n, (int64_t)((16 - (addr & 15)) & 15));
+        in.nbody = (in.n - in.head) / 16;
+        in.hist = hist;
+        hist += (int64_t)(q.max_iter + 2) * (q.n_clusters + 2);
+        in.C = q.n_clusters;
+        in.mclass = (q.m == 2.0) ? kM2 : (q.m == 1.5 ? kM15 : kMGeneric);
+        in.max_iter = q.max_iter;
+        in.kahan_only = (q.flags & FCM_F_KAHAN_ONLY) ? 1 : 0;
+        in.given = start_mode(q.init);
+        in.dv0 = q.init == FCM_INIT_DEVICE ? q.init_centroids : nullptr;
+        in.alpha = (float)(1.0 / (q.m - 1.0));
+        in.mexp = (float)q.m;
+        in.eps = q.eps;
+        for (int k = 0; k < kMaxC; ++k) in.v0[k] = b->given[(size_t)i * kMaxC + k];
+    }
+    b->hist_total = hist;
+    hipError_t e;
+    if ((e = hipGetDevice(&b->device)) != hipSuccess) return fail(dev_err(e, "hipGetDevice"));
+    if ((e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess)
+        return fail(dev_err(e, "hipDeviceGetAttribute"));
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device) != hipSuccess || !coop)
+        return fail(FCM_EUNSUPPORTED);
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || clock_khz <= 0)
+        clock_khz = 100000;
+    b->spin_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
+    if ((e = batch_max_grid(b->ncu, &b->max_grid)) != hipSuccess) return fail(dev_err(e, "occupancy"));
+    b->max_grid = std::max(1, std::min(b->max_grid, kMaxPersistGrid));
+
+    if (hipMalloc(&b->d_inst, sizeof(BatchInst) * count) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_recs, sizeof(BatchRec) * count) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_hist, sizeof(double) * hist) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_dec, sizeof(uint64_t) * kBatchDecWords * count) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_sync, sizeof(BatchSync)) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipHostMalloc(&b->h_recs, sizeof(BatchRec) * count, hipHostMallocDefault) != hipSuccess)
+        return fail(FCM_ENOMEM);
+    if (hipHostMalloc(&b->h_sync, sizeof(BatchSync), hipHostMallocDefault) != hipSuccess) return fail(FCM_ENOMEM);
+    if ((e = hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * count, b->stream)) != hipSuccess)
+        return fail(dev_err(e, "hipMemsetAsync"));
+    if ((e = hipMemsetAsync(b->d_recs, 0, sizeof(BatchRec) * count, b->stream)) != hipSuccess)
+        return fail(dev_err(e, "hipMemsetAsync"));
+    int rc = batch_build_tiles(b);
+    if (rc != FCM_OK) return fail(rc);
+    *out = b;
+    return FCM_OK;
+}
+
+int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid) {
+    if (!b || chunks_per_thread < 1 || chunks_per_thread > 64 || grid < 0 || grid > kMaxPersistGrid)
+        return FCM_EINVAL;
+    b->chunks_per_thread = chunks_per_thread;
+    b->grid_req = grid;
+    b->solved = false;
+    FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
+    return batch_build_tiles(b);
+}
+
+int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
+    if (!b || !out) return FCM_EINVAL;
+    int max_iter = 1;
+    for (const fcm_params& q : b->p) max_iter = std::max(max_iter, q.max_iter);
+    b->h_sync->gen_max = b->round;
+    b->h_sync->abort = 0;
+    b->h_sync->active = (uint32_t)b->count;
+    b->h_sync->pad = 0;
+    FCM_HIP(hipMemcpyAsync(b->d_sync, b->h_sync, sizeof(BatchSync), hipMemcpyHostToDevice, b->stream));
+    BatchArgs a{};
+    a.x = b->d_x;
+    a.inst = b->d_inst;
+    a.tiles = b->d_tiles;
+    a.recs = b->d_recs;
+    a.hist = b->d_hist;
+    a.rows = b->d_rows;
+    a.mm = b->d_mm;
+    a.dec = b->d_dec;
+    a.sync = b->d_sync;
+    a.I = b->count;
+    a.ntiles = (int32_t)b->h_tiles.size();
+    a.do_init = 1;
+    a.max_sweeps = max_iter + 2;
+    a.round0 = b->round;
+    a.spin_ticks = b->spin_ticks;
+    hipError_t e = launch_batch(a, b->grid, b->stream);
+    if (e != hipSuccess) return dev_err(e, "hipLaunchCooperativeKernel (batch)");
+    FCM_HIP(hipMemcpyAsync(b->h_recs, b->d_recs, sizeof(BatchRec) * b->count, hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipStreamSynchronize(b->stream));
+    if (b->h_sync->abort) {
+        g_last_error = "a cross-block wait of the batched solve exceeded its time limit";
+        // clear every tagged buffer so that the next solve starts clean
+        FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
+        int rc = batch_build_tiles(b);
+        return rc != FCM_OK ? rc : FCM_EDEVICE;
+    }
+    b->round = b->h_sync->gen_max;
+    b->solved = true;
+    int worst = FCM_OK;
+    for (int32_t i = 0; i < b->count; ++i) {
+        const BatchRec& r = b->h_recs[i];
+        fcm_result& o = out[i];
+        std::memset(&o, 0, sizeof(o));
+        o.iters = r.iters < 0 ? 0 : r.iters;
+        o.passes = r.passes;
+        o.status = r.status;
+        o.n_clusters = b->p[i].n_clusters;
+        o.delta = r.delta;
+        o.J = r.J;
+        for (int k = 0; k < o.n_clusters; ++k) o.centroids[k] = r.vres[k];
+        o.lo = r.lo;
+        o.hi = r.hi;
+        if (r.status == FCM_ENUMERIC) worst = FCM_ENUMERIC;
+        else if (r.status != FCM_OK && worst == FCM_OK) worst = r.status;
+    }
+    return worst;
+}
+
+int fcm_batch_labels(fcm_batch* b, uint8_t* d_labels) {
+    if (!b || !d_labels) return FCM_EINVAL;
+    if (!b->solved) return FCM_ESTATE;
+    BatchLabelArgs a{};
+    a.x = b->d_x;
+    a.labels = d_labels;
+    a.inst = b->d_inst;
+    a.tiles = b->d_tiles;
+    a.recs = b->d_recs;
+    a.hist = b->d_hist;
+    a.ntiles = (int32_t)b->h_tiles.size();
+    a.bytewise = (((uintptr_t)b->d_x ^ (uintptr_t)d_labels) & 15) ? 1 : 0;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.ntiles, 4LL * b->ncu));
+    hipError_t e = launch_batch_labels(a, grid, b->stream);
+    if (e != hipSuccess) return dev_err(e, "launch_batch_labels");
+    return FCM_OK;
+}
+
+int fcm_batch_trajectory(fcm_batch* b, int32_t inst, int32_t t, double* v_out, double* delta, double* J) {
+    if (!b || inst < 0 || inst >= b->count) return FCM_EINVAL;
+    if (!b->solved) return FCM_ESTATE;
+    const BatchRec& r = b->h_recs[inst];
+    if (t < 0 || t > r.iters) return FCM_EINVAL;
+    const BatchInst& in = b->h_inst[inst];
+    const int C = in.C;
+    const double* hv = b->d_hist + in.hist;
+    const double* hd = hv + (int64_t)(in.max_iter + 2) * C;
+    const double* hJ = hd + (in.max_iter + 2);
+    double row[kMaxC + 2];
+    FCM_HIP(hipMemcpyAsync(row, hv + (int64_t)t * C, sizeof(double) * C, hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipMemcpyAsync(row + C, hd + t, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipMemcpyAsync(row + C + 1, hJ + t, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipStreamSynchronize(b->stream));
+    if (v_out) std::memcpy(v_out, row, sizeof(double) * C);
+    if (delta) *delta = row[C];
+    if (J) *J = row[C + 1];
+    return FCM_OK;
+}
+
+void fcm_batch_destroy(fcm_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
 }
 
 }  // extern "C"

@@ -101,3 +101,23 @@ def test_null_handle_calls(lib):
     assert lib.fcm_set_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
     assert lib.fcm_get_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
     lib.fcm_destroy(None)
+
+
+def test_batch_init_validation(lib):
+    b = ctypes.c_void_p()
+    recs = (L.FcmParams * 2)(_params(), _params())
+    off = (ctypes.c_int64 * 3)(0, 100, 250)
+    assert lib.fcm_batch_init(ctypes.byref(b), None, off, 2, recs, None) == L.FCM_EINVAL
+    assert lib.fcm_batch_init(ctypes.byref(b), FAKE, off, 0, recs, None) == L.FCM_EINVAL
+    bad_off = (ctypes.c_int64 * 3)(1, 100, 250)
+    assert lib.fcm_batch_init(ctypes.byref(b), FAKE, bad_off, 2, recs, None) == L.FCM_EINVAL
+    empty = (ctypes.c_int64 * 3)(0, 100, 100)
+    assert lib.fcm_batch_init(ctypes.byref(b), FAKE, empty, 2, recs, None) == L.FCM_EINVAL
+    bad = (L.FcmParams * 2)(_params(), _params(n_clusters=9))
+    assert lib.fcm_batch_init(ctypes.byref(b), FAKE, off, 2, bad, None) == L.FCM_EINVAL
+    r = (L.FcmResult * 2)()
+    assert lib.fcm_batch_solve(None, r) == L.FCM_EINVAL
+    assert lib.fcm_batch_labels(None, FAKE) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_tiling(None, 4, 0) == L.FCM_EINVAL
+    assert lib.fcm_batch_trajectory(None, 0, 0, None, None, None) == L.FCM_EINVAL
+    lib.fcm_batch_destroy(None)

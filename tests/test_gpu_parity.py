@@ -52,9 +52,9 @@ def check_against_literal(torch_dev, x, C, m=2.0, eps=1e-5, max_iter=300, init=N
     assert res.status in (0, 1)
     if res.iters != ora.T:
         ora_ext = fcm_ref.solve(x, C, m, 0.0, max(res.iters, ora.T) + 1, v0=ora.v[0])
-        P.check_iterations(res, ora.T, ora_ext, eps)
+        P.check_iterations(res, ora.T, ora_ext, eps, hist=fcm_hist.histogram(x), m=m, gpu_vs=traj[0])
         ora = ora_ext
-    err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
+    err = P.compare(res, traj, ora, eps, hist=fcm_hist.histogram(x), m=m)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     assert res.passes == res.iters + 1
     return res, ora, err, amb
@@ -258,9 +258,9 @@ def check_against_levels(torch_dev, x, C, m, eps=1e-5, **kw):
     ora = fcm_hist.solve(h, C, m, eps, 300)
     if res.iters != ora.T:
         ora_ext = fcm_hist.solve(h, C, m, 0.0, max(res.iters, ora.T) + 1, v0=ora.v[0])
-        P.check_iterations(res, ora.T, ora_ext, eps)
+        P.check_iterations(res, ora.T, ora_ext, eps, hist=h, m=m, gpu_vs=traj[0])
         ora = ora_ext
-    err = P.compare(res, traj, ora, eps, n=np.asarray(x).size)
+    err = P.compare(res, traj, ora, eps, hist=h, m=m)
     amb = P.check_labels(x, lab, ora.v[res.iters])
     return res, err, amb
 
