@@ -65,7 +65,7 @@ extern "C" {
 /* iteration drivers */
 #define FCM_DRIVER_LOOP   0     /* one launch per pass from the host */
 #define FCM_DRIVER_GRAPH  1     /* a hipGraph of graph_k passes, replayed */
-#define FCM_DRIVER_PERSISTENT 2 /* one cooperative launch runs the data-range pass
+#define FCM_DRIVER_PERSISTENT 2 /* one persistent launch runs the data-range pass
                                    and every pass of a solve (default where
                                    supported) */
 
@@ -73,6 +73,15 @@ extern "C" {
 #define FCM_EXCHANGE_AUTO      0  /* all-gather on small grids, else leader */
 #define FCM_EXCHANGE_LEADER    1  /* block 0 reduces and broadcasts the decision */
 #define FCM_EXCHANGE_ALLGATHER 2  /* every block reduces every partial row itself */
+
+/* how the persistent driver launches its kernel */
+#define FCM_LAUNCH_COOPERATIVE 0  /* hipLaunchCooperativeKernel: the runtime guarantees
+                                     that every block is resident at once (about 15 us
+                                     more dispatch time per solve on MI355X) */
+#define FCM_LAUNCH_RESIDENT    1  /* default: ordinary launch of a grid no larger than the
+                                     device holds at once.  Another kernel occupying the
+                                     device can delay some blocks; a wait that exceeds the
+                                     time limit (5 s) ends the solve with FCM_EDEVICE */
 
 typedef struct fcm_params {
     int32_t n_clusters;           /* C, 2..FCM_MAX_CLUSTERS */
@@ -95,6 +104,7 @@ typedef struct fcm_tuning {
     int32_t graph_k;    /* loop/graph drivers: passes per host synchronisation
                            (and per graph), 1..64 */
     int32_t exchange;   /* persistent driver: FCM_EXCHANGE_* */
+    int32_t launch;     /* persistent driver: FCM_LAUNCH_* */
 } fcm_tuning;
 
 typedef struct fcm_result {

@@ -32,6 +32,8 @@ FCM_DRIVER_PERSISTENT = 2
 FCM_EXCHANGE_AUTO = 0
 FCM_EXCHANGE_LEADER = 1
 FCM_EXCHANGE_ALLGATHER = 2
+FCM_LAUNCH_COOPERATIVE = 0
+FCM_LAUNCH_RESIDENT = 1
 
 # every symbol include/fcm.h declares
 EXPORTS = (
@@ -62,6 +64,7 @@ class FcmTuning(ctypes.Structure):
         ("driver", ctypes.c_int32),
         ("graph_k", ctypes.c_int32),
         ("exchange", ctypes.c_int32),
+        ("launch", ctypes.c_int32),
     ]
 
 

@@ -45,12 +45,15 @@ hipError_t persist_max_grid(int C, int mclass, int unroll, int ncu, int* max_gri
     return hipSuccess;
 }
 
-hipError_t launch_persist(const PassArgs& a, int C, int mclass, int unroll, int grid, hipStream_t s) {
+hipError_t launch_persist(const PassArgs& a, int C, int mclass, int unroll, int grid, bool cooperative,
+                          hipStream_t s) {
     PassFn f = pick(C, mclass, unroll, true);
     if (!f) return hipErrorInvalidValue;
     PassArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3(grid), dim3(kBlock), args, 0, s);
+    if (cooperative)
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3(grid), dim3(kBlock), args, 0, s);
+    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 }  // namespace fcm

@@ -172,6 +172,7 @@ hipError_t launch_pass(const PassArgs& a, int C, int mclass, int unroll, int gri
 hipError_t launch_labels(const LabelArgs& a, int grid, hipStream_t s);
 bool pass_supported(int C, int mclass, int unroll);
 hipError_t persist_max_grid(int C, int mclass, int unroll, int ncu, int* max_grid);
-hipError_t launch_persist(const PassArgs& a, int C, int mclass, int unroll, int grid, hipStream_t s);
+hipError_t launch_persist(const PassArgs& a, int C, int mclass, int unroll, int grid, bool cooperative,
+                          hipStream_t s);
 
 }  // namespace fcm

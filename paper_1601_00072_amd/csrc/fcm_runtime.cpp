@@ -71,6 +71,7 @@ int validate_tuning(const fcm_tuning* t) {
         return FCM_EINVAL;
     if (t->graph_k < 1 || t->graph_k > kMaxGraphK) return FCM_EINVAL;
     if (t->exchange < FCM_EXCHANGE_AUTO || t->exchange > FCM_EXCHANGE_ALLGATHER) return FCM_EINVAL;
+    if (t->launch != FCM_LAUNCH_COOPERATIVE && t->launch != FCM_LAUNCH_RESIDENT) return FCM_EINVAL;
     return FCM_OK;
 }
 
@@ -265,8 +266,9 @@ int run_batch(fcm_handle* h, int batch) {
             if (rc != FCM_OK) return rc;
             FCM_HIP(hipEventRecord(h->ev[0], h->stream));
         }
-        hipError_t e = launch_persist(a, h->p.n_clusters, h->mclass, h->tun.unroll, h->grid, h->stream);
-        if (e != hipSuccess) return dev_err(e, "hipLaunchCooperativeKernel");
+        hipError_t e = launch_persist(a, h->p.n_clusters, h->mclass, h->tun.unroll, h->grid,
+                                      h->tun.launch == FCM_LAUNCH_COOPERATIVE, h->stream);
+        if (e != hipSuccess) return dev_err(e, "persistent launch");
         h->pending_init = false;
         if (timing) FCM_HIP(hipEventRecord(h->ev[1], h->stream));
         int rc = read_state(h);
@@ -420,6 +422,7 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     h->tun.driver = h->coop ? FCM_DRIVER_PERSISTENT : FCM_DRIVER_GRAPH;
     h->tun.graph_k = 8;
     h->tun.exchange = FCM_EXCHANGE_AUTO;
+    h->tun.launch = FCM_LAUNCH_RESIDENT;
     if ((rc = resolve_grid(h, &h->grid)) != FCM_OK) return fail(rc);
 
     if (hipMalloc(&h->d_state, sizeof(DevState)) != hipSuccess) return fail(FCM_ENOMEM);

@@ -91,7 +91,7 @@ def test_init_rejects_bad_pointers_and_sizes(lib):
 
 def test_null_handle_calls(lib):
     r = L.FcmResult()
-    t = L.FcmTuning(block=256, grid=0, unroll=1, driver=1, graph_k=8, exchange=0)
+    t = L.FcmTuning(block=256, grid=0, unroll=1, driver=1, graph_k=8, exchange=0, launch=0)
     buf = (ctypes.c_double * 8)()
     assert lib.fcm_iterate(None, 1, ctypes.byref(r)) == L.FCM_EINVAL
     assert lib.fcm_solve(None, ctypes.byref(r)) == L.FCM_EINVAL

@@ -102,13 +102,14 @@ def test_launch_shapes(torch_dev, grid, unroll, driver, exchange):
     check_against_literal(torch_dev, x, 4, tuning=dict(grid=grid, unroll=unroll, driver=driver, exchange=exchange))
 
 
-@pytest.mark.parametrize("driver,k,exchange", [(0, 1, 0), (0, 5, 0), (1, 1, 0), (1, 3, 0), (1, 16, 0), (2, 1, 0),
-                                               (2, 1, 1), (2, 1, 2)])
+@pytest.mark.parametrize("driver,k,exchange,launch", [(0, 1, 0, 0), (0, 5, 0, 0), (1, 1, 0, 0), (1, 3, 0, 0),
+                                                      (1, 16, 0, 0), (2, 1, 0, 0), (2, 1, 1, 0), (2, 1, 2, 0),
+                                                      (2, 1, 0, 1), (2, 1, 1, 1), (2, 1, 2, 1)])
 @pytest.mark.parametrize("shape", [(200, 200), (32, 160, 160)])
-def test_drivers(torch_dev, driver, k, exchange, shape):
-    announce("driver", driver, "graph_k", k, "exchange", exchange, "shape", shape)
+def test_drivers(torch_dev, driver, k, exchange, launch, shape):
+    announce("driver", driver, "graph_k", k, "exchange", exchange, "launch", launch, "shape", shape)
     x = phantom(PhantomParams(shape=shape, seed=1))
-    check_against_literal(torch_dev, x, 4, tuning=dict(driver=driver, graph_k=k, exchange=exchange))
+    check_against_literal(torch_dev, x, 4, tuning=dict(driver=driver, graph_k=k, exchange=exchange, launch=launch))
 
 
 # --- cluster counts and fuzziness -------------------------------------------
