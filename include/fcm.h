@@ -200,6 +200,105 @@ int fcm_batch_trajectory(fcm_batch* b, int32_t inst, int32_t t, double* v_out, d
 
 void fcm_batch_destroy(fcm_batch* b);
 
+/* ---- learned warm start -------------------------------------------------
+ * A small network maps the normalised 256-bin grey-level histogram of an
+ * instance to start centroids: 256 -> 128 (ReLU) -> 64 (ReLU) -> C (linear),
+ * output = centroids / 255.  The fuzzy objective J_m (Eq.1) is what FCM
+ * minimises; the network only proposes v^0, and Algorithm 1 is then run from
+ * there exactly as from any other start.  Parameters are one flat FP32
+ * vector: W1 [256][128], b1 [128], W2 [128][64], b2 [64], W3 [64][C], b3 [C]
+ * (row-major, [in][out]).  Training: FP32 forward and backward on the GPU,
+ * mean squared error over the batch and the C outputs, Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected).  Inference for warm starts: BF16
+ * weights and activations (round to nearest even), FP32 accumulation.  All
+ * reductions run in a fixed order: the same calls give the same bits.
+ * A network belongs to the stream given at creation; its parameters must not
+ * change while inference that reads them runs on another stream. */
+typedef struct fcm_mlp fcm_mlp;
+
+#define FCM_MLP_FP32 0
+#define FCM_MLP_BF16 1
+
+typedef struct fcm_train_cfg {
+    int32_t  epochs;   /* passes over the training set, >= 1 */
+    int32_t  batch;    /* minibatch size, 1..4096 (the last batch of an epoch may be smaller) */
+    float    lr;       /* Adam step size, finite and > 0 */
+    uint32_t pad;
+    uint64_t seed;     /* order of the samples: a Fisher-Yates shuffle per epoch
+                          drawn from a SplitMix64 counter generator */
+} fcm_train_cfg;
+
+/* Number of parameters of the network with C outputs (41,412 for C = 4), or
+ * FCM_EINVAL for C outside 2..8. */
+int32_t fcm_mlp_param_count(int32_t C);
+
+/* Create a network with C outputs, He-initialised (weights N(0, 2 / fan_in)
+ * from a SplitMix64 counter generator and Box-Muller keyed by seed; biases
+ * 0), Adam state zero.  Allocates its parameters, optimiser state and
+ * workspace on the current device. */
+int fcm_mlp_create(fcm_mlp** net, int32_t C, uint64_t seed, void* stream);
+
+/* Copy the flat parameter vector to / from host memory (fcm_mlp_param_count
+ * floats).  Setting parameters also clears the Adam state.  Both wait for
+ * the stream. */
+int fcm_mlp_get_params(fcm_mlp* net, float* out);
+int fcm_mlp_set_params(fcm_mlp* net, const float* in);
+
+/* Inference: d_out[count][C] = network(d_hist[count][256]) in FP32
+ * (FCM_MLP_FP32) or BF16 (FCM_MLP_BF16) arithmetic.  Device buffers,
+ * caller-owned; count >= 1.  Enqueued, not waited for. */
+int fcm_mlp_forward(fcm_mlp* net, const float* d_hist, int32_t count, float* d_out, int32_t precision);
+
+/* Loss and gradient at the current parameters on one batch (no update):
+ * *loss = sum (y - t)^2 / (count C); grad (host, may be NULL) receives the
+ * flat gradient.  d_target[count][C] holds centroids / 255.  Grows the
+ * workspace if count exceeds it; waits for the stream. */
+int fcm_mlp_loss_grad(fcm_mlp* net, const float* d_hist, const float* d_target, int32_t count, double* loss,
+                      float* grad);
+
+/* Train on d_hist[count][256], d_target[count][C] (device): cfg->epochs
+ * epochs of shuffled minibatches, one Adam step each.  epoch_loss (host,
+ * cfg->epochs doubles, may be NULL) receives the mean training loss of every
+ * epoch.  Waits for the stream. */
+int fcm_mlp_train(fcm_mlp* net, const float* d_hist, const float* d_target, int32_t count, const fcm_train_cfg* cfg,
+                  double* epoch_loss);
+
+void fcm_mlp_destroy(fcm_mlp* net);
+
+/* Normalised 256-bin histograms (each row sums to 1) of the instances
+ * d_x[offsets[i] .. offsets[i+1]) (offsets: count + 1 host values, starting
+ * at 0, non-decreasing, every instance non-empty) into d_hist[count][256].
+ * Allocates and frees temporaries; waits for the stream. */
+int fcm_histogram(const uint8_t* d_x, const int64_t* offsets, int32_t count, float* d_hist, void* stream);
+
+/* Start centroids from histograms: BF16 inference, then v = 255 y sorted
+ * ascending, clamped to the instance's grey-level range [lo, hi] (read off
+ * its histogram), consecutive gaps of at least 1.  d_v0[count][C] doubles
+ * (device); a row is NaN where no such set exists (non-finite output, or
+ * fewer than C grey levels in the range), which FCM_INIT_DEVICE reads as
+ * "use the evenly spaced start".  Grows a scratch buffer if needed; enqueued
+ * on the stream, not waited for. */
+int fcm_warm_centroids(fcm_mlp* net, const float* d_hist, int32_t count, double* d_v0, void* stream);
+
+/* Warm-started solve on a handle (whose C must equal the network's): the
+ * histogram of the handle's input, the network's start centroids, then
+ * Algorithm 1 from them, all on the handle's stream; the handle afterwards
+ * holds that solve (labels, trajectory).  check != 0: also solve from the
+ * handle's own start (the plain result, copied to *plain if non-NULL) and
+ * keep the warm result only if J_warm <= J_plain (1 + 1e-6); otherwise the
+ * plain solve is run again so that the handle holds it, and *used = 0.
+ * used (may be NULL): 1 if the returned result is the warm-started one.
+ * The first call allocates a small workspace (histogram, start). */
+int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain, int32_t* used);
+
+/* Start of each batch instance for the following fcm_batch_solve calls:
+ * instance i takes the network's start centroids if net != NULL, its C
+ * equals the network's, and use_learned (count host flags, NULL = all) is
+ * nonzero for it; every other instance takes its own init from
+ * fcm_batch_init.  Computes the histograms and runs the network on the
+ * batch's stream (allocating their buffers on the first call). */
+int fcm_batch_set_start(fcm_batch* b, fcm_mlp* net, const uint8_t* use_learned);
+
 /* Static description of a status code, and the last HIP error text of this thread. */
 const char* fcm_strerror(int status);
 const char* fcm_last_error(void);

@@ -7,6 +7,12 @@ error over the batch and the C outputs, L = sum (y - t)^2 / (B C).
 Parameters are kept as one flat vector in the order W1 (256 x 128, row-major),
 b1, W2 (128 x 64), b2, W3 (64 x C), b3.  Adam: the standard update with bias
 correction (beta1 = 0.9, beta2 = 0.999, eps = 1e-8).
+
+BF16 inference: bfloat16 keeps 8 significant bits (1 implicit + 7 stored)
+and the FP32 exponent range; values are rounded to nearest, ties to even.
+`forward_bf16` rounds the input, every weight and bias, and every hidden
+activation to BF16 and sums exactly (FP64), so it differs from a BF16 kernel
+with FP32 accumulation only by that accumulation's rounding.
 """
 from __future__ import annotations
 
@@ -74,3 +80,18 @@ def adam_step(theta, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def bf16_round(v):
+    """Round to the nearest BF16 value, ties to even (finite, normal inputs)."""
+    v = np.asarray(v, dtype=np.float64)
+    m, e = np.frexp(v)                 # v = m 2^e, |m| in [0.5, 1)
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)   # 8 significant bits; rint ties to even
+
+
+def forward_bf16(theta, X, C):
+    W1, b1, W2, b2, W3, b3 = (bf16_round(w) for w in unpack(np.asarray(theta, dtype=np.float64), C))
+    a0 = bf16_round(np.asarray(X, dtype=np.float64))
+    a1 = bf16_round(np.maximum(a0 @ W1 + b1, 0.0))
+    a2 = bf16_round(np.maximum(a1 @ W2 + b2, 0.0))
+    return a2 @ W3 + b3

@@ -3,6 +3,6 @@
 PyTorch supplies device memory and streams; every step of the iteration runs
 in the library's HIP kernels.
 """
-from .api import FCM, FCMBatch, FcmError, Result, solve
+from .api import FCM, MLP, FCMBatch, FcmError, Result, histogram, solve
 
-__all__ = ["FCM", "FCMBatch", "FcmError", "Result", "solve"]
+__all__ = ["FCM", "FCMBatch", "MLP", "FcmError", "Result", "histogram", "solve"]

@@ -24,6 +24,9 @@ FCM_EUNSUPPORTED = -6
 FCM_MAX_CLUSTERS = 8
 FCM_INIT_LINSPACE = 0
 FCM_INIT_GIVEN = 1
+FCM_INIT_DEVICE = 2
+FCM_MLP_FP32 = 0
+FCM_MLP_BF16 = 1
 FCM_F_KAHAN_ONLY = 1 << 0
 FCM_F_TIMING = 1 << 1
 FCM_DRIVER_LOOP = 0
@@ -40,7 +43,9 @@ EXPORTS = (
     "fcm_init", "fcm_reset", "fcm_set_tuning", "fcm_get_tuning", "fcm_iterate", "fcm_solve", "fcm_labels",
     "fcm_centroids", "fcm_trajectory", "fcm_destroy", "fcm_strerror", "fcm_last_error", "fcm_version",
     "fcm_batch_init", "fcm_batch_set_tiling", "fcm_batch_solve", "fcm_batch_labels", "fcm_batch_trajectory",
-    "fcm_batch_destroy",
+    "fcm_batch_destroy", "fcm_mlp_param_count", "fcm_mlp_create", "fcm_mlp_get_params", "fcm_mlp_set_params",
+    "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
+    "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start",
 )
 
 
@@ -80,6 +85,16 @@ class FcmResult(ctypes.Structure):
         ("kernel_ms", ctypes.c_double),
         ("lo", ctypes.c_int32),
         ("hi", ctypes.c_int32),
+    ]
+
+
+class FcmTrainCfg(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("lr", ctypes.c_float),
+        ("pad", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -139,5 +154,31 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_trajectory.restype = ctypes.c_int
     lib.fcm_batch_destroy.argtypes = [vp]
     lib.fcm_batch_destroy.restype = None
+    f32p, f64p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+    lib.fcm_mlp_param_count.argtypes = [i32]
+    lib.fcm_mlp_param_count.restype = i32
+    lib.fcm_mlp_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp]
+    lib.fcm_mlp_create.restype = ctypes.c_int
+    lib.fcm_mlp_get_params.argtypes = [vp, f32p]
+    lib.fcm_mlp_get_params.restype = ctypes.c_int
+    lib.fcm_mlp_set_params.argtypes = [vp, f32p]
+    lib.fcm_mlp_set_params.restype = ctypes.c_int
+    lib.fcm_mlp_forward.argtypes = [vp, vp, i32, vp, i32]
+    lib.fcm_mlp_forward.restype = ctypes.c_int
+    lib.fcm_mlp_loss_grad.argtypes = [vp, vp, vp, i32, f64p, f32p]
+    lib.fcm_mlp_loss_grad.restype = ctypes.c_int
+    lib.fcm_mlp_train.argtypes = [vp, vp, vp, i32, ctypes.POINTER(FcmTrainCfg), f64p]
+    lib.fcm_mlp_train.restype = ctypes.c_int
+    lib.fcm_mlp_destroy.argtypes = [vp]
+    lib.fcm_mlp_destroy.restype = None
+    lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
+    lib.fcm_histogram.restype = ctypes.c_int
+    lib.fcm_warm_centroids.argtypes = [vp, vp, i32, vp, vp]
+    lib.fcm_warm_centroids.restype = ctypes.c_int
+    lib.fcm_solve_warm.argtypes = [vp, vp, i32, ctypes.POINTER(FcmResult), ctypes.POINTER(FcmResult),
+                                   ctypes.POINTER(i32)]
+    lib.fcm_solve_warm.restype = ctypes.c_int
+    lib.fcm_batch_set_start.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint8)]
+    lib.fcm_batch_set_start.restype = ctypes.c_int
     _lib = lib
     return lib

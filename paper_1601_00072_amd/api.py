@@ -142,6 +142,18 @@ class FCM:
                     "fcm_trajectory")
         return np.array(v[:], dtype=np.float64), d.value, J.value
 
+    def solve_warm(self, net: "MLP", check: bool = False):
+        """Solve from the network's start centroids (histogram -> BF16 network
+        -> start).  check: also solve from the handle's own start and keep the
+        warm result only if its J is within 1e-6 (relative) of the plain one,
+        else fall back.  Returns (result, used_warm, plain result or None)."""
+        r, rp, used = L.FcmResult(), L.FcmResult(), ctypes.c_int32()
+        rc = self._lib.fcm_solve_warm(self._h, net._h, 1 if check else 0, ctypes.byref(r), ctypes.byref(rp),
+                                      ctypes.byref(used))
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_solve_warm")
+        return _result(r), bool(used.value), (_result(rp) if check else None)
+
     # -- lifetime -------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):
@@ -232,6 +244,44 @@ class FCMBatch:
             raise FcmError(rc, "fcm_batch_solve")
         return [_result(r) for r in out]
 
+    def set_start(self, net: "MLP | None" = None, use=None):
+        """Learned start for the instances whose C matches the network (and
+        whose flag in `use` is set, if given); every other instance, or all
+        with net=None, takes its own init."""
+        flags = None
+        if use is not None:
+            buf = np.ascontiguousarray(np.asarray(use, dtype=np.uint8))
+            if buf.shape != (self.count,):
+                raise ValueError("one flag per instance")
+            flags = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        rc = self._lib.fcm_batch_set_start(self._h, None if net is None else net._h, flags)
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_set_start")
+
+    def solve_warm(self, net: "MLP", check: bool = True):
+        """Warm-started batch solve with the fall-back rule per instance: with
+        check, instance i keeps its warm result only if J_warm <= J_plain (1 +
+        1e-6); the instances that fall back are solved again from their own
+        start in a final launch, so that labels and trajectories match the
+        returned results.  Returns (results, used_warm flags, plain results or
+        None); the batch keeps the starts of the returned results (set_start()
+        goes back to each instance's own init)."""
+        plain = None
+        if check:
+            self.set_start(None)
+            plain = self.solve()
+        self.set_start(net)
+        warm = self.solve()
+        used = np.array([c == net.C for c in self.C], dtype=bool)
+        if check:
+            ok = np.array([u and w.status != L.FCM_ENUMERIC and w.J <= p.J * (1.0 + 1e-6)
+                           for u, w, p in zip(used, warm, plain)], dtype=bool)
+            if not np.array_equal(ok, used):
+                self.set_start(net, ok)
+                warm = self.solve()
+            used = ok
+        return warm, used, plain
+
     def labels(self, out=None):
         import torch
         if out is None:
@@ -266,3 +316,130 @@ class FCMBatch:
             self.close()
         except Exception:
             pass
+
+
+def histogram(x, sizes, stream=None):
+    """Normalised 256-bin histograms of the instances packed back to back in
+    the uint8 device tensor x; returns a float32 device tensor [count, 256]."""
+    import torch
+    lib = L.load()
+    off = np.concatenate([[0], np.cumsum([int(v) for v in sizes])]).astype(np.int64)
+    if off[-1] != x.numel():
+        raise ValueError("sizes must add up to x.numel()")
+    out = torch.empty((len(sizes), 256), dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    rc = lib.fcm_histogram(ctypes.c_void_p(x.data_ptr()), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           len(sizes), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+    if rc != L.FCM_OK:
+        raise FcmError(rc, "fcm_histogram")
+    return out
+
+
+class MLP:
+    """Histogram -> centroid network (256 -> 128 -> 64 -> C), trained and run
+    by the library's kernels.  Inputs are normalised histograms (float32
+    device tensors [B, 256]); outputs and targets are centroids / 255."""
+
+    def __init__(self, n_clusters: int, seed: int = 0, stream=None):
+        import torch
+        self._lib = L.load()
+        self.C = int(n_clusters)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        rc = self._lib.fcm_mlp_create(ctypes.byref(self._h), self.C, ctypes.c_uint64(seed),
+                                      ctypes.c_void_p(self._stream.cuda_stream))
+        if rc != L.FCM_OK:
+            self._h = None
+            raise FcmError(rc, "fcm_mlp_create")
+        self.n_params = int(self._lib.fcm_mlp_param_count(self.C))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.fcm_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "fcm_mlp_get_params")
+        return out
+
+    def set_params(self, theta):
+        buf = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        if buf.shape != (self.n_params,):
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._check(self._lib.fcm_mlp_set_params(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "fcm_mlp_set_params")
+
+    def forward(self, hist, bf16: bool = False):
+        import torch
+        hist = self._dev2d(hist, 256)
+        out = torch.empty((hist.shape[0], self.C), dtype=torch.float32, device=hist.device)
+        self._check(self._lib.fcm_mlp_forward(self._h, ctypes.c_void_p(hist.data_ptr()), hist.shape[0],
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              L.FCM_MLP_BF16 if bf16 else L.FCM_MLP_FP32), "fcm_mlp_forward")
+        return out
+
+    def loss_grad(self, hist, target):
+        hist, target = self._dev2d(hist, 256), self._dev2d(target, self.C)
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.fcm_mlp_loss_grad(self._h, ctypes.c_void_p(hist.data_ptr()),
+                                                ctypes.c_void_p(target.data_ptr()), hist.shape[0],
+                                                ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "fcm_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, hist, target, epochs: int, batch: int = 256, lr: float = 1e-3, seed: int = 0):
+        hist, target = self._dev2d(hist, 256), self._dev2d(target, self.C)
+        cfg = L.FcmTrainCfg(epochs=int(epochs), batch=int(batch), lr=float(lr), pad=0, seed=int(seed))
+        losses = np.empty(int(epochs), dtype=np.float64)
+        self._check(self._lib.fcm_mlp_train(self._h, ctypes.c_void_p(hist.data_ptr()),
+                                            ctypes.c_void_p(target.data_ptr()), hist.shape[0], ctypes.byref(cfg),
+                                            losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "fcm_mlp_train")
+        return losses
+
+    def warm_centroids(self, hist):
+        """Start centroids [B, C] (float64 device tensor; NaN rows = no valid start)."""
+        import torch
+        hist = self._dev2d(hist, 256)
+        out = torch.empty((hist.shape[0], self.C), dtype=torch.float64, device=hist.device)
+        self._check(self._lib.fcm_warm_centroids(self._h, ctypes.c_void_p(hist.data_ptr()), hist.shape[0],
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.c_void_p(self._stream.cuda_stream)), "fcm_warm_centroids")
+        return out
+
+    def save(self, path: str):
+        np.save(path, self.params())
+
+    def load(self, path: str):
+        self.set_params(np.load(path, allow_pickle=False))
+
+    @staticmethod
+    def _dev2d(t, cols):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+            raise TypeError("expected a float32 CUDA/HIP tensor")
+        t = t.contiguous()
+        if t.dim() != 2 or t.shape[1] != cols or t.shape[0] < 1:
+            raise ValueError(f"expected shape [B, {cols}]")
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fcm_mlp_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if self._h is None:
+            raise FcmError(L.FCM_ESTATE, what)
+        if rc != L.FCM_OK:
+            raise FcmError(rc, what)

@@ -5,7 +5,16 @@
 
 #include <hip/hip_runtime.h>
 
+struct fcm_mlp;
+
 namespace fcm {
+
+// Output width C of a network, and its warm start: BF16 inference of `count`
+// normalised histograms into d_y (count x C) and the post-processing into
+// start centroids d_v0 (count x C doubles; a row of NaN where no valid start
+// exists).  Enqueued on s; returns an FCM_* status.
+int mlp_clusters(const fcm_mlp* net);
+int mlp_warm(fcm_mlp* net, const float* d_hist, int count, float* d_y, double* d_v0, hipStream_t s);
 
 hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
                             float* hist, hipStream_t s);
@@ -17,7 +26,7 @@ hipError_t launch_adam(float* theta, const float* g, float* m, float* v, int64_t
                        hipStream_t s);
 hipError_t launch_gather(const float* X, const int32_t* idx, int rows, int cols, float* out, hipStream_t s);
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
-hipError_t launch_mlp_infer_bf16(const uint16_t* wb, const float* X, int count, int C, float* Y, hipStream_t s);
+hipError_t launch_mlp_infer(const void* w, bool bf16, const float* X, int count, int C, float* Y, hipStream_t s);
 hipError_t launch_warm_post(const float* Y, const float* hist, int count, int C, double* v0, hipStream_t s);
 
 }  // namespace fcm

@@ -70,8 +70,13 @@ hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int coun
     int64_t gx64 = (chunks + kBlock * 16 - 1) / (kBlock * 16);
     gx64 = gx64 < 1 ? 1 : (gx64 > 64 ? 64 : gx64);
     const int gx = (int)gx64;
-    hipLaunchKernelGGL(hist_count_kernel, dim3(gx, count), dim3(kBlock), 0, s, x, d_offsets, counts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    constexpr int kMaxY = 65535;  // grid y limit: instances per launch
+    for (int c0 = 0; c0 < count; c0 += kMaxY) {
+        const int cnt = count - c0 < kMaxY ? count - c0 : kMaxY;
+        hipLaunchKernelGGL(hist_count_kernel, dim3(gx, cnt), dim3(kBlock), 0, s, x, d_offsets + c0,
+                           counts + (int64_t)c0 * 256);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(hist_norm_kernel, dim3(count), dim3(256), 0, s, counts, d_offsets, hist);
     return hipGetLastError();
 }
@@ -244,42 +249,60 @@ hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t
     return hipGetLastError();
 }
 
-// One block (128 threads) per histogram: the three layers with BF16 weights
-// and activations, FP32 accumulation; output y[C] in FP32.
-__global__ __launch_bounds__(128) void mlp_infer_bf16_kernel(const uint16_t* wb, const float* X, int C, float* Y) {
+// One block (128 threads) per histogram: the three layers in a fixed order of
+// summation, FP32 accumulation.  BF16: weights and activations (the input
+// histogram included) rounded to BF16 before every product; otherwise FP32
+// weights and activations.  Output y[C] in FP32.
+template <bool BF16>
+__device__ __forceinline__ float wload(const void* w, int64_t i) {
+    if constexpr (BF16)
+        return from_bf16(static_cast<const uint16_t*>(w)[i]);
+    else
+        return static_cast<const float*>(w)[i];
+}
+
+template <bool BF16>
+__device__ __forceinline__ float act(float v) {
+    if constexpr (BF16)
+        return from_bf16(to_bf16(v));
+    else
+        return v;
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(128) void mlp_infer_kernel(const void* w, const float* X, int C, float* Y) {
     __shared__ float a0[256];
     __shared__ float a1[128];
     __shared__ float a2[64];
     const int s = blockIdx.x, t = threadIdx.x;
-    const uint16_t* W1 = wb;
-    const uint16_t* b1 = W1 + 256 * 128;
-    const uint16_t* W2 = b1 + 128;
-    const uint16_t* b2 = W2 + 128 * 64;
-    const uint16_t* W3 = b2 + 64;
-    const uint16_t* b3 = W3 + 64 * C;
-    for (int i = t; i < 256; i += 128) a0[i] = from_bf16(to_bf16(X[(int64_t)s * 256 + i]));
+    constexpr int64_t oW1 = 0, ob1 = oW1 + 256 * 128, oW2 = ob1 + 128, ob2 = oW2 + 128 * 64, oW3 = ob2 + 64;
+    const int64_t ob3 = oW3 + 64 * (int64_t)C;
+    for (int i = t; i < 256; i += 128) a0[i] = act<BF16>(X[(int64_t)s * 256 + i]);
     __syncthreads();
     {
-        float z = from_bf16(b1[t]);
-        for (int i = 0; i < 256; ++i) z = fmaf(a0[i], from_bf16(W1[i * 128 + t]), z);
-        a1[t] = from_bf16(to_bf16(fmaxf(z, 0.f)));
+        float z = wload<BF16>(w, ob1 + t);
+        for (int i = 0; i < 256; ++i) z = fmaf(a0[i], wload<BF16>(w, oW1 + i * 128 + t), z);
+        a1[t] = act<BF16>(fmaxf(z, 0.f));
     }
     __syncthreads();
     if (t < 64) {
-        float z = from_bf16(b2[t]);
-        for (int i = 0; i < 128; ++i) z = fmaf(a1[i], from_bf16(W2[i * 64 + t]), z);
-        a2[t] = from_bf16(to_bf16(fmaxf(z, 0.f)));
+        float z = wload<BF16>(w, ob2 + t);
+        for (int i = 0; i < 128; ++i) z = fmaf(a1[i], wload<BF16>(w, oW2 + i * 64 + t), z);
+        a2[t] = act<BF16>(fmaxf(z, 0.f));
     }
     __syncthreads();
     if (t < C) {
-        float z = from_bf16(b3[t]);
-        for (int i = 0; i < 64; ++i) z = fmaf(a2[i], from_bf16(W3[i * C + t]), z);
+        float z = wload<BF16>(w, ob3 + t);
+        for (int i = 0; i < 64; ++i) z = fmaf(a2[i], wload<BF16>(w, oW3 + i * C + t), z);
         Y[(int64_t)s * C + t] = z;
     }
 }
 
-hipError_t launch_mlp_infer_bf16(const uint16_t* wb, const float* X, int count, int C, float* Y, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3(count), dim3(128), 0, s, wb, X, C, Y);
+hipError_t launch_mlp_infer(const void* w, bool bf16, const float* X, int count, int C, float* Y, hipStream_t s) {
+    if (bf16)
+        hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(count), dim3(128), 0, s, w, X, C, Y);
+    else
+        hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(count), dim3(128), 0, s, w, X, C, Y);
     return hipGetLastError();
 }
 

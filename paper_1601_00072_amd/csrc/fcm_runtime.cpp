@@ -20,24 +20,27 @@
 #include <vector>
 
 #include "fcm.h"
+#include "fcm_host.h"
 #include "fcm_internal.h"
+#include "fcm_learn.h"
 
 using namespace fcm;
 
-namespace {
+namespace fcm {
 
-thread_local std::string g_last_error;
+std::string& last_error() {
+    thread_local std::string text;
+    return text;
+}
 
 int dev_err(hipError_t e, const char* what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    last_error() = std::string(what) + ": " + hipGetErrorString(e);
     return FCM_EDEVICE;
 }
 
-#define FCM_HIP(call)                                         \
-    do {                                                      \
-        hipError_t e_ = (call);                               \
-        if (e_ != hipSuccess) return dev_err(e_, #call);      \
-    } while (0)
+}  // namespace fcm
+
+namespace {
 
 constexpr uint32_t kKnownFlags = FCM_F_KAHAN_ONLY | FCM_F_TIMING;
 constexpr int kMaxGraphK = 64;
@@ -112,6 +115,13 @@ struct fcm_handle {
 
     std::vector<hipEvent_t> ev;
     double kernel_ms = 0.0;
+
+    // warm start workspace (first fcm_solve_warm)
+    int64_t* d_woff = nullptr;     // {0, n}
+    uint32_t* d_wcounts = nullptr; // [256]
+    float* d_whist = nullptr;      // [256]
+    float* d_wy = nullptr;         // [kMaxC] network output
+    double* d_wv0 = nullptr;       // [kMaxC] learned start
 
     double* hist_v() const { return d_hist; }
     double* hist_d() const { return d_hist + (int64_t)(p.max_iter + 2) * p.n_clusters; }
@@ -201,7 +211,7 @@ int read_state(fcm_handle* h) {
     FCM_HIP(hipStreamSynchronize(h->stream));
     if (h->h_state->sync.abort) {
         h->aborted = true;
-        g_last_error = "a cross-block wait exceeded its time limit; the solve was aborted (reset the handle)";
+        last_error() = "a cross-block wait exceeded its time limit; the solve was aborted (reset the handle)";
         return FCM_EDEVICE;
     }
     return FCM_OK;
@@ -354,6 +364,8 @@ void release(fcm_handle* h) {
     if (h->d_rows) (void)hipFree(h->d_rows);
     if (h->d_mmrows) (void)hipFree(h->d_mmrows);
     if (h->d_hist) (void)hipFree(h->d_hist);
+    for (void* p : {(void*)h->d_woff, (void*)h->d_wcounts, (void*)h->d_whist, (void*)h->d_wy, (void*)h->d_wv0})
+        if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
     delete h;
 }
@@ -379,7 +391,7 @@ const char* fcm_strerror(int status) {
     }
 }
 
-const char* fcm_last_error(void) { return g_last_error.c_str(); }
+const char* fcm_last_error(void) { return last_error().c_str(); }
 
 int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* p, void* stream) {
     if (!out || !d_x || n < 1) return FCM_EINVAL;
@@ -509,6 +521,53 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
     return out->status;
 }
 
+int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain, int32_t* used) {
+    if (!h || !net || !out) return FCM_EINVAL;
+    if (mlp_clusters(net) != h->p.n_clusters) return FCM_EINVAL;
+    if (!h->d_woff) {
+        if (hipMalloc(&h->d_wcounts, sizeof(uint32_t) * 256) != hipSuccess) return FCM_ENOMEM;
+        if (hipMalloc(&h->d_whist, sizeof(float) * 256) != hipSuccess) return FCM_ENOMEM;
+        if (hipMalloc(&h->d_wy, sizeof(float) * kMaxC) != hipSuccess) return FCM_ENOMEM;
+        if (hipMalloc(&h->d_wv0, sizeof(double) * kMaxC) != hipSuccess) return FCM_ENOMEM;
+        int64_t* off = nullptr;
+        if (hipMalloc(&off, sizeof(int64_t) * 2) != hipSuccess) return FCM_ENOMEM;
+        const int64_t range[2] = {0, h->n};
+        FCM_HIP(hipMemcpyAsync(off, range, sizeof(range), hipMemcpyHostToDevice, h->stream));
+        FCM_HIP(hipStreamSynchronize(h->stream));
+        h->d_woff = off;
+    }
+    fcm_result rp{}, rw{};
+    int rc;
+    if (check) {  // the plain solve from the handle's own start
+        if ((rc = enqueue_start(h)) != FCM_OK) return rc;
+        if ((rc = fcm_solve(h, &rp)) < 0) return rc;
+    }
+    // learned start: histogram -> network (BF16) -> start centroids, then Algorithm 1
+    FCM_HIP(launch_histogram(h->d_x, h->d_woff, 1, h->n, h->d_wcounts, h->d_whist, h->stream));
+    if ((rc = mlp_warm(net, h->d_whist, 1, h->d_wy, h->d_wv0, h->stream)) != FCM_OK) return rc;
+    const int32_t own_init = h->p.init;
+    const double* own_dv0 = h->dv0;
+    h->p.init = FCM_INIT_DEVICE;
+    h->dv0 = h->d_wv0;
+    rc = enqueue_start(h);
+    if (rc == FCM_OK) rc = fcm_solve(h, &rw);
+    h->p.init = own_init;
+    h->dv0 = own_dv0;
+    if (rc < 0) return rc;
+    int use = 1;
+    if (check) {
+        use = rw.status != FCM_ENUMERIC && rw.J <= rp.J * (1.0 + 1e-6);
+        if (plain) *plain = rp;
+        if (!use) {  // fall back: run the plain solve again so that the handle holds it
+            if ((rc = enqueue_start(h)) != FCM_OK) return rc;
+            if ((rc = fcm_solve(h, &rw)) < 0) return rc;
+        }
+    }
+    *out = rw;
+    if (used) *used = use;
+    return out->status;
+}
+
 int fcm_labels(fcm_handle* h, uint8_t* d_labels) {
     if (!h || !d_labels) return FCM_EINVAL;
     int rc = flush_init(h);
@@ -575,6 +634,7 @@ struct fcm_batch {
     std::vector<int64_t> offsets;
     std::vector<fcm_params> p;
     std::vector<double> given;  // count * kMaxC
+    std::vector<const double*> own_dv0;  // FCM_INIT_DEVICE start arrays of the caller
     hipStream_t stream = nullptr;
     int device = 0, ncu = 256, max_grid = 1, grid = 1, grid_req = 0;
     int chunks_per_thread = 4;
@@ -597,6 +657,13 @@ struct fcm_batch {
     int64_t tiles_cap = 0;     // capacity of d_tiles / d_rows / d_mm
     BatchRec* h_recs = nullptr;
     BatchSync* h_sync = nullptr;
+
+    // learned starts (first fcm_batch_set_start with a network)
+    int64_t* d_off = nullptr;      // offsets [count + 1]
+    uint32_t* d_counts = nullptr;  // [count][256]
+    float* d_whist = nullptr;      // [count][256]
+    float* d_wy = nullptr;         // [count][kMaxC]
+    double* d_wv0 = nullptr;       // [count][kMaxC]
 };
 
 namespace {
@@ -621,6 +688,8 @@ void batch_release(fcm_batch* b) {
     if (b->d_sync) (void)hipFree(b->d_sync);
     if (b->h_recs) (void)hipHostFree(b->h_recs);
     if (b->h_sync) (void)hipHostFree(b->h_sync);
+    for (void* p : {(void*)b->d_off, (void*)b->d_counts, (void*)b->d_whist, (void*)b->d_wy, (void*)b->d_wv0})
+        if (p) (void)hipFree(p);
     delete b;
 }
 
@@ -690,6 +759,7 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
     b->offsets.assign(offsets, offsets + count + 1);
     b->p.assign(params, params + count);
     b->given.assign((size_t)count * kMaxC, 0.0);
+    b->own_dv0.assign((size_t)count, nullptr);
     b->stream = (hipStream_t)stream;
     b->h_inst.resize(count);
     int64_t hist = 0;
@@ -713,6 +783,7 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
         in.kahan_only = (q.flags & FCM_F_KAHAN_ONLY) ? 1 : 0;
         in.given = start_mode(q.init);
         in.dv0 = q.init == FCM_INIT_DEVICE ? q.init_centroids : nullptr;
+        b->own_dv0[(size_t)i] = in.dv0;
         in.alpha = (float)(1.0 / (q.m - 1.0));
         in.mexp = (float)q.m;
         in.eps = q.eps;
@@ -761,6 +832,45 @@ int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid) 
     return batch_build_tiles(b);
 }
 
+int fcm_batch_set_start(fcm_batch* b, fcm_mlp* net, const uint8_t* use_learned) {
+    if (!b) return FCM_EINVAL;
+    const int C = net ? mlp_clusters(net) : 0;
+    if (net) {
+        const size_t cnt = (size_t)b->count;
+        if (!b->d_off) {
+            if (hipMalloc(&b->d_counts, sizeof(uint32_t) * 256 * cnt) != hipSuccess) return FCM_ENOMEM;
+            if (hipMalloc(&b->d_whist, sizeof(float) * 256 * cnt) != hipSuccess) return FCM_ENOMEM;
+            if (hipMalloc(&b->d_wy, sizeof(float) * kMaxC * cnt) != hipSuccess) return FCM_ENOMEM;
+            if (hipMalloc(&b->d_wv0, sizeof(double) * kMaxC * cnt) != hipSuccess) return FCM_ENOMEM;
+            int64_t* off = nullptr;
+            if (hipMalloc(&off, sizeof(int64_t) * (cnt + 1)) != hipSuccess) return FCM_ENOMEM;
+            FCM_HIP(hipMemcpyAsync(off, b->offsets.data(), sizeof(int64_t) * (cnt + 1), hipMemcpyHostToDevice,
+                                   b->stream));
+            FCM_HIP(hipStreamSynchronize(b->stream));
+            b->d_off = off;
+        }
+        int64_t max_n = 1;
+        for (int32_t i = 0; i < b->count; ++i) max_n = std::max<int64_t>(max_n, b->h_inst[i].n);
+        FCM_HIP(launch_histogram(b->d_x, b->d_off, b->count, max_n, b->d_counts, b->d_whist, b->stream));
+        int rc = mlp_warm(net, b->d_whist, b->count, b->d_wy, b->d_wv0, b->stream);
+        if (rc != FCM_OK) return rc;
+    }
+    for (int32_t i = 0; i < b->count; ++i) {
+        BatchInst& in = b->h_inst[i];
+        if (net && in.C == C && (!use_learned || use_learned[i])) {
+            in.given = 2;
+            in.dv0 = b->d_wv0 + (int64_t)i * C;
+        } else {
+            in.given = start_mode(b->p[i].init);
+            in.dv0 = b->own_dv0[(size_t)i];
+        }
+    }
+    FCM_HIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice,
+                           b->stream));
+    FCM_HIP(hipStreamSynchronize(b->stream));  // the host table may change after return
+    return FCM_OK;
+}
+
 int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
     if (!b || !out) return FCM_EINVAL;
     int max_iter = 1;
@@ -792,7 +902,7 @@ int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
     FCM_HIP(hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, b->stream));
     FCM_HIP(hipStreamSynchronize(b->stream));
     if (b->h_sync->abort) {
-        g_last_error = "a cross-block wait of the batched solve exceeded its time limit";
+        last_error() = "a cross-block wait of the batched solve exceeded its time limit";
         // clear every tagged buffer so that the next solve starts clean
         FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
         int rc = batch_build_tiles(b);
