@@ -237,8 +237,113 @@ def batched(dev):
             "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b}
 
 
+# ---- learned warm start (training set, held-out slices and volumes) ----------
+
+_SHARED = None  # anonymous shared mapping filled by forked workers
+
+
+def _fill(job):
+    import numpy as np
+
+    from phantom import jittered_params, phantom
+    shape, seeds, offs = job
+    view = np.frombuffer(_SHARED, dtype=np.uint8)
+    n = int(np.prod(shape))
+    for sd, o in zip(seeds, offs):
+        view[o:o + n] = phantom(jittered_params(shape, sd)).ravel()
+    return len(seeds)
+
+
+def learned_sets(workers: int):
+    """The warm start's data: 20,000 training slices 256x256 (seeds 1e6 + i),
+    1,024 held-out slices 256x256 (seeds 2e6 + i) and 64 held-out volumes
+    128^3 (seeds 3e6 + i), each phantom with its own jittered parameters.
+    Generated by forked workers into one shared mapping, before the process
+    touches the GPU.  Returns {name: (uint8 array, shape, count)}."""
+    import mmap
+    import multiprocessing as mp
+
+    import numpy as np
+    global _SHARED
+    spec = [("train", (256, 256), 20000, 10 ** 6), ("slices", (256, 256), 1024, 2 * 10 ** 6),
+            ("volumes", (128, 128, 128), 64, 3 * 10 ** 6)]
+    total, base = 0, {}
+    for name, shape, count, _ in spec:
+        base[name] = total
+        total += int(np.prod(shape)) * count
+    _SHARED = mmap.mmap(-1, total)
+    jobs = []
+    for name, shape, count, seed0 in spec:
+        n = int(np.prod(shape))
+        step = 1 if len(shape) == 3 else 250
+        for i0 in range(0, count, step):
+            ids = range(i0, min(count, i0 + step))
+            jobs.append((shape, [seed0 + i for i in ids], [base[name] + i * n for i in ids]))
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_fill, jobs, chunksize=1)
+    buf = np.frombuffer(_SHARED, dtype=np.uint8)
+    return {name: (buf[base[name]:base[name] + int(np.prod(shape)) * count], shape, count)
+            for name, shape, count, _ in spec}
+
+
+def learned(dev, sets, x_head, C, m, eps, steps):
+    """Train the network on GPU-converged centroids of the training slices,
+    then compare warm and plain starts on the held-out sets (one handle per
+    instance, and all in one batched launch) and on the headline volume."""
+    import numpy as np
+    import torch
+
+    from paper_1601_00072_amd import FCM, learn
+    out = {}
+    arr, shape, count = sets["train"]
+    x = torch.from_numpy(np.asarray(arr)).to(dev)
+    sizes = [int(np.prod(shape))] * count
+    net, losses, t_tgt, t_train = learn.train(x, sizes, C=4, epochs=100, batch=256, lr=1e-3, seed=1)
+    out["training"] = {"phantoms": count, "shape": list(shape), "epochs": 100, "batch": 256, "lr": 1e-3,
+                       "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+                       "s_targets_gpu_fcm": t_tgt, "s_training": t_train}
+    del x
+    print(f"# learned: trained ({t_train:.2f} s), loss {losses[0]:.3e} -> {losses[-1]:.3e}", file=sys.stderr,
+          flush=True)
+    for name in ("slices", "volumes"):
+        arr, shape, count = sets[name]
+        x = torch.from_numpy(np.asarray(arr)).to(dev)
+        sizes = [int(np.prod(shape))] * count
+        out[name] = {"per_instance": learn.evaluate_instances(net, x, sizes, C=4),
+                     "batched": learn.evaluate_batch(net, x, sizes, C=4)}
+        print(f"# learned: {name} done", file=sys.stderr, flush=True)
+        del x
+    # the headline volume: time to converge, plain vs warm start
+    with FCM(x_head, C, m=m, eps=eps) as f:
+        rw, used, rp = f.solve_warm(net, check=True)
+        f.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f.reset()
+            f.solve()
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f.solve_warm(net, check=False)
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - t0) / steps
+    out["headline_volume"] = {"iters_plain": rp.iters, "iters_warm": rw.iters, "warm_accepted": used,
+                              "rel_J_gap": (rw.J - rp.J) / rp.J, "ms_to_converge_plain": tp * 1e3,
+                              "ms_to_converge_warm": tw * 1e3,
+                              "warm_includes": "histogram + BF16 network + start post-processing + solve"}
+    net.close()
+    return out
+
+
 def main():
     args = parse()
+    sets = None
+    if not args.quick and not args.copy_probe and args.gpus == 1:
+        t0 = time.perf_counter()
+        sets = learned_sets(min(16, os.cpu_count() or 1))
+        print(f"# learned-start data generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -319,7 +424,8 @@ def main():
         print(f"# large volume: {lv['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
         bt = batched(dev)
         print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
-        out["extra"] = {"large_volume": lv, "batched": bt}
+        ln = learned(dev, sets, x, C, m, eps, args.steps)
+        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -121,3 +121,33 @@ def test_batch_init_validation(lib):
     assert lib.fcm_batch_set_tiling(None, 4, 0) == L.FCM_EINVAL
     assert lib.fcm_batch_trajectory(None, 0, 0, None, None, None) == L.FCM_EINVAL
     lib.fcm_batch_destroy(None)
+
+
+def test_learned_start_validation(lib):
+    """Argument checks of the warm-start entry points (before any HIP call)."""
+    assert lib.fcm_mlp_param_count(4) == 256 * 128 + 128 + 128 * 64 + 64 + 64 * 4 + 4 == 41412
+    assert lib.fcm_mlp_param_count(8) == 41412 + 4 * 64 + 4
+    assert lib.fcm_mlp_param_count(1) == L.FCM_EINVAL
+    assert lib.fcm_mlp_param_count(9) == L.FCM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.fcm_mlp_create(None, 4, 0, None) == L.FCM_EINVAL
+    assert lib.fcm_mlp_create(ctypes.byref(h), 1, 0, None) == L.FCM_EINVAL
+    assert lib.fcm_mlp_create(ctypes.byref(h), 9, 0, None) == L.FCM_EINVAL
+    buf = (ctypes.c_float * 8)()
+    assert lib.fcm_mlp_get_params(None, buf) == L.FCM_EINVAL
+    assert lib.fcm_mlp_set_params(None, buf) == L.FCM_EINVAL
+    assert lib.fcm_mlp_forward(None, FAKE, 1, FAKE, 0) == L.FCM_EINVAL
+    loss = ctypes.c_double()
+    assert lib.fcm_mlp_loss_grad(None, FAKE, FAKE, 1, ctypes.byref(loss), buf) == L.FCM_EINVAL
+    cfg = L.FcmTrainCfg(epochs=1, batch=16, lr=1e-3, pad=0, seed=0)
+    assert lib.fcm_mlp_train(None, FAKE, FAKE, 10, ctypes.byref(cfg), None) == L.FCM_EINVAL
+    lib.fcm_mlp_destroy(None)
+    off = (ctypes.c_int64 * 3)(0, 10, 10)  # second instance empty
+    assert lib.fcm_histogram(FAKE, off, 2, FAKE, None) == L.FCM_EINVAL
+    off = (ctypes.c_int64 * 2)(1, 10)      # does not start at 0
+    assert lib.fcm_histogram(FAKE, off, 1, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_histogram(None, off, 1, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_warm_centroids(None, FAKE, 1, FAKE, None) == L.FCM_EINVAL
+    r = L.FcmResult()
+    assert lib.fcm_solve_warm(None, None, 0, ctypes.byref(r), None, None) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_start(None, None, None) == L.FCM_EINVAL

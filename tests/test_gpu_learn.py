@@ -299,4 +299,4 @@ def test_trained_network_gain(torch_dev):
     net.close()
     assert losses[-1] < 0.1 * losses[0]
     assert ev["iters_warm_mean"] < ev["iters_plain_mean"]
-    assert ev["max_rel_J_gap_accepted"] <= 1e-6
+    assert ev["max_rel_J_excess_accepted"] <= 1e-6
