@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--launch", choices=("cooperative", "resident"), default="resident",
                     help="launch of the persistent solve kernel")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 5 times (counter calibration)")
     return ap.parse_args()
@@ -180,15 +181,17 @@ def large_volume(dev):
     x = torch.from_numpy(phantom(PhantomParams(shape=shape, seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
     n = x.numel()
     f = FCM(x, 4, timing=True)
+    f.autotune(reps=2)
     timed_solves(f, 1)
     el, passes, kms, r = timed_solves(f, 3)
+    tun = f.tuning
     f.close()
     launch_s = kms / 3 * 1e-3
     ach = roofline(n, 4, 2.0, r.passes, launch_s)
     return {"workload": "ellipsoid-shell phantom 512x512x256 (67,108,864 voxels), seed 3, sigma 9, bias 20%, "
                         "C=4, m=2, eps=1e-5",
             "iterations": r.iters, "ms_per_solve": el / 3 * 1e3, "voxel_iterations_per_s": n * passes / el,
-            "us_per_pass": launch_s / r.passes * 1e6,
+            "us_per_pass": launch_s / r.passes * 1e6, "tuning": tun,
             "roofline_frac": ach / PEAK_LANE_OPS, "achieved_T_lane_op_s": ach / 1e12}
 
 
@@ -373,8 +376,12 @@ def main():
 
     f = FCM(x, C, m=m, eps=eps, max_iter=300, timing=True, stream=stream)
     f.set_tuning(launch=0 if args.launch == "cooperative" else 1)
+    tuned_ms = None
+    if not args.no_autotune:
+        _, tuned_ms = f.autotune(reps=3)
     timed_solves(f, args.warmup, labels)
-    print(f"# warmup done, tuning {f.tuning}", file=sys.stderr, flush=True)
+    tuning = f.tuning
+    print(f"# warmup done, tuning {tuning}", file=sys.stderr, flush=True)
     el, passes_total, kernel_ms_total, r = timed_solves(f, args.steps, labels)
     f.close()
     print(f"# timed {args.steps} solves: T={r.iters} status={r.status}", file=sys.stderr, flush=True)
@@ -404,6 +411,8 @@ def main():
             "time_to_converge_ms": ms_per_step,
             "step": "data-range pass + fused passes to convergence + labels (one persistent launch + labels)",
             "launch": args.launch,
+            "tuning": tuning,
+            "autotuned": not args.no_autotune,
             "paper_context": "0.08 s at 40 KB and 2.33 s at 1 MB on a Tesla C2050 (Table 3), context only",
         },
         "roofline": {

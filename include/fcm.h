@@ -200,6 +200,33 @@ int fcm_batch_trajectory(fcm_batch* b, int32_t inst, int32_t t, double* v_out, d
 
 void fcm_batch_destroy(fcm_batch* b);
 
+/* ---- autotuner ------------------------------------------------------------
+ * Both calls time whole solves on the object's own data (host wall clock
+ * around reset + solve, the median of `reps` runs, 1..100) for a set of
+ * candidate launch configurations, keep the fastest candidate whose result
+ * agrees with the configuration in place at entry (same iteration count and
+ * centroids within 1e-5 relative, or one iteration apart and within 1e-4),
+ * apply it, and return it.  cache_path (may be NULL): a text file of earlier
+ * choices, one line each, keyed by device, HIP runtime version and problem
+ * class; a matching entry is applied without timing, and a new choice is
+ * appended.  Choices are also cached per process.  The data must not change
+ * during the call. */
+
+/* Single instance: persistent driver (ordinary launch) over grids from half
+ * the CU count up to one 16-voxel chunk per thread, leader and all-gather
+ * exchange, unroll 1 and 2; graph driver with 4 and 16 passes per graph.
+ * Key: C, the m class (2, 1.5, other), the precision flag and floor(log2 n).
+ * The handle is left reset with the chosen tuning (chosen may be NULL; ms:
+ * the chosen configuration's median solve time, may be NULL). */
+int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning* chosen, double* ms);
+
+/* Batch: tiles of 1, 2, 4, 8 or 16 chunks per thread, on the largest grid
+ * the device holds and on half of it.  Key: instance count, largest C and
+ * floor(log2 of the total voxels).  The chosen tiling is applied
+ * (fcm_batch_set_tiling); outputs may be NULL. */
+int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* chunks_per_thread, int32_t* grid,
+                       double* ms);
+
 /* ---- learned warm start -------------------------------------------------
  * A small network maps the normalised 256-bin grey-level histogram of an
  * instance to start centroids: 256 -> 128 (ReLU) -> 64 (ReLU) -> C (linear),

@@ -45,7 +45,7 @@ EXPORTS = (
     "fcm_batch_init", "fcm_batch_set_tiling", "fcm_batch_solve", "fcm_batch_labels", "fcm_batch_trajectory",
     "fcm_batch_destroy", "fcm_mlp_param_count", "fcm_mlp_create", "fcm_mlp_get_params", "fcm_mlp_set_params",
     "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
-    "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start",
+    "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
 )
 
 
@@ -180,5 +180,9 @@ def load() -> ctypes.CDLL:
     lib.fcm_solve_warm.restype = ctypes.c_int
     lib.fcm_batch_set_start.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint8)]
     lib.fcm_batch_set_start.restype = ctypes.c_int
+    lib.fcm_autotune.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(FcmTuning), f64p]
+    lib.fcm_autotune.restype = ctypes.c_int
+    lib.fcm_batch_autotune.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), f64p]
+    lib.fcm_batch_autotune.restype = ctypes.c_int
     _lib = lib
     return lib

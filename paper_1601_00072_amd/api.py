@@ -102,6 +102,15 @@ class FCM:
         t = L.FcmTuning(**cur)
         self._check(self._lib.fcm_set_tuning(self._h, ctypes.byref(t)), "fcm_set_tuning")
 
+    def autotune(self, cache: str | None = None, reps: int = 3):
+        """Time candidate launch configurations on this input and keep the
+        fastest that agrees with the current one (see fcm_autotune).
+        Returns (tuning dict, median ms per solve)."""
+        t, ms = L.FcmTuning(), ctypes.c_double()
+        self._check(self._lib.fcm_autotune(self._h, None if cache is None else str(cache).encode(), int(reps),
+                                           ctypes.byref(t), ctypes.byref(ms)), "fcm_autotune")
+        return {f: getattr(t, f) for f, _ in L.FcmTuning._fields_}, ms.value
+
     # -- iteration --------------------------------------------------------------
     def reset(self):
         """Restart from v^0 on the same (possibly rewritten) input; no allocation."""
@@ -243,6 +252,16 @@ class FCMBatch:
         if rc < 0 and rc != L.FCM_ENUMERIC:
             raise FcmError(rc, "fcm_batch_solve")
         return [_result(r) for r in out]
+
+    def autotune(self, cache: str | None = None, reps: int = 2):
+        """Pick the tile size and grid (see fcm_batch_autotune); returns
+        (chunks_per_thread, grid, median ms per batched solve)."""
+        cpt, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        rc = self._lib.fcm_batch_autotune(self._h, None if cache is None else str(cache).encode(), int(reps),
+                                          ctypes.byref(cpt), ctypes.byref(grid), ctypes.byref(ms))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_autotune")
+        return cpt.value, grid.value, ms.value
 
     def set_start(self, net: "MLP | None" = None, use=None):
         """Learned start for the instances whose C matches the network (and

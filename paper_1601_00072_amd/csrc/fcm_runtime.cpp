@@ -976,3 +976,33 @@ void fcm_batch_destroy(fcm_batch* b) {
 }
 
 }  // extern "C"
+
+namespace fcm {
+
+int handle_shape(const fcm_handle* h, HandleShape* s) {
+    if (!h || !s) return FCM_EINVAL;
+    s->n = h->n;
+    s->nbody = h->nbody;
+    s->C = h->p.n_clusters;
+    s->mclass = h->mclass;
+    s->kahan = (h->p.flags & FCM_F_KAHAN_ONLY) ? 1 : 0;
+    s->device = h->device;
+    s->ncu = h->ncu;
+    s->coop = h->coop;
+    return FCM_OK;
+}
+
+int batch_shape(const fcm_batch* b, BatchShape* s) {
+    if (!b || !s) return FCM_EINVAL;
+    s->voxels = b->offsets.back();
+    s->count = b->count;
+    s->max_C = 0;
+    for (const fcm_params& q : b->p) s->max_C = std::max(s->max_C, (int)q.n_clusters);
+    s->device = b->device;
+    s->max_grid = b->max_grid;
+    s->chunks_per_thread = b->chunks_per_thread;
+    s->grid = b->grid_req;
+    return FCM_OK;
+}
+
+}  // namespace fcm

@@ -1,0 +1,311 @@
+// Autotuner of the launch configuration (C ABI declared in include/fcm.h).
+//
+// It measures what a caller gets: whole solves (reset + solve, host wall
+// clock around the call, which waits for the stream) on the caller's own
+// data, for every candidate configuration, and keeps the fastest one whose
+// result agrees with the handle's configuration at entry (same iteration
+// count, or one apart, and centroids within 1e-5 relative; 1e-4 when the
+// counts differ by one).  Choices are cached per process and, if a path is
+// given, in a text file (one line per choice, the last matching line wins),
+// keyed by device, HIP runtime version, C, the m class, the precision
+// variant and the size bucket (floor(log2 n)).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fcm.h"
+#include "fcm_host.h"
+#include "fcm_internal.h"
+
+using namespace fcm;
+
+namespace {
+
+constexpr int kMaxAllGatherGrid = 512;  // larger all-gather grids flood the fabric with polls
+
+struct Choice {
+    int32_t v[7];   // single: driver grid unroll exchange launch graph_k; batch: chunks_per_thread grid
+    double ms;
+};
+
+std::mutex g_mu;
+std::map<std::string, Choice> g_cache;
+
+std::string device_tag(int device) {
+    hipDeviceProp_t p;
+    std::memset(&p, 0, sizeof(p));
+    int rv = 0;
+    (void)hipGetDeviceProperties(&p, device);
+    (void)hipRuntimeGetVersion(&rv);
+    std::string arch = p.gcnArchName[0] ? p.gcnArchName : "unknown";
+    for (char& c : arch)
+        if (c == ' ' || c == '\t') c = '_';
+    return arch + "/" + std::to_string(p.multiProcessorCount) + "cu/hip" + std::to_string(rv);
+}
+
+int log2_floor(int64_t n) {
+    int b = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+bool load_choice(const char* path, const std::string& key, int nv, Choice* out) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            *out = it->second;
+            return true;
+        }
+    }
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        // fcm-tune1 \\t key \\t values... ms
+        const size_t a = line.find('\t'), b = a == std::string::npos ? a : line.find('\t', a + 1);
+        if (a == std::string::npos || b == std::string::npos) continue;
+        if (line.compare(0, a, "fcm-tune1") != 0 || line.compare(a + 1, b - a - 1, key) != 0) continue;
+        std::istringstream in(line.substr(b + 1));
+        Choice c{};
+        bool ok = true;
+        for (int i = 0; i < nv && ok; ++i) ok = static_cast<bool>(in >> c.v[i]);
+        ok = ok && static_cast<bool>(in >> c.ms);
+        if (ok) {
+            *out = c;
+            found = true;
+        }
+    }
+    if (found) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = *out;
+    }
+    return found;
+}
+
+void store_choice(const char* path, const std::string& key, int nv, const Choice& c) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = c;
+    }
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    f << "fcm-tune1\t" << key << "\t";
+    for (int i = 0; i < nv; ++i) f << c.v[i] << ' ';
+    f << c.ms << '\n';
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+bool agrees(const fcm_result& a, const fcm_result& ref) {
+    if (a.status != ref.status && !(a.status >= 0 && ref.status >= 0)) return false;
+    const int dt = std::abs(a.iters - ref.iters);
+    if (dt > 1) return false;
+    const double tol = dt == 0 ? 1e-5 : 1e-4;
+    for (int k = 0; k < ref.n_clusters; ++k) {
+        const double d = std::fabs(a.centroids[k] - ref.centroids[k]);
+        if (!(d <= tol * std::max(std::fabs(ref.centroids[k]), 1.0))) return false;
+    }
+    return true;
+}
+
+// median wall time of `reps` whole solves; < 0 if a call failed
+double time_single(fcm_handle* h, int reps, fcm_result* last) {
+    std::vector<double> t;
+    for (int i = 0; i < reps; ++i) {
+        const double t0 = now_ms();
+        if (fcm_reset(h) != FCM_OK) return -1.0;
+        const int rc = fcm_solve(h, last);
+        if (rc < 0 && rc != FCM_ENUMERIC) return -1.0;
+        t.push_back(now_ms() - t0);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+double time_batch(fcm_batch* b, int reps, std::vector<fcm_result>& last) {
+    std::vector<double> t;
+    for (int i = 0; i < reps; ++i) {
+        const double t0 = now_ms();
+        const int rc = fcm_batch_solve(b, last.data());
+        if (rc < 0 && rc != FCM_ENUMERIC) return -1.0;
+        t.push_back(now_ms() - t0);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning* chosen, double* ms) {
+    if (!h || reps < 1 || reps > 100) return FCM_EINVAL;
+    HandleShape s{};
+    int rc = handle_shape(h, &s);
+    if (rc != FCM_OK) return rc;
+    std::ostringstream key;
+    key << "single " << device_tag(s.device) << " C=" << s.C << " mclass=" << s.mclass << " kahan=" << s.kahan
+        << " nlog2=" << log2_floor(s.n);
+    fcm_tuning entry{};
+    if ((rc = fcm_get_tuning(h, &entry)) != FCM_OK) return rc;
+    Choice c{};
+    if (load_choice(cache_path, key.str(), 6, &c)) {
+        fcm_tuning t = entry;
+        t.driver = c.v[0];
+        t.grid = c.v[1];
+        t.unroll = c.v[2];
+        t.exchange = c.v[3];
+        t.launch = c.v[4];
+        t.graph_k = c.v[5];
+        if (fcm_set_tuning(h, &t) == FCM_OK) {
+            if (chosen) (void)fcm_get_tuning(h, chosen);
+            if (ms) *ms = c.ms;
+            return fcm_reset(h);
+        }
+        // a cached choice this handle cannot take: tune afresh
+    }
+
+    // reference: the configuration at entry
+    fcm_result ref{}, r{};
+    if ((rc = fcm_reset(h)) != FCM_OK) return rc;
+    rc = fcm_solve(h, &ref);
+    if (rc < 0 && rc != FCM_ENUMERIC) return rc;
+
+    std::vector<fcm_tuning> cand;
+    const int64_t full = std::max<int64_t>(1, (s.nbody + kBlock - 1) / kBlock);
+    std::vector<int> grids;
+    for (int64_t g : {full, (int64_t)s.ncu / 2, (int64_t)s.ncu, (int64_t)2 * s.ncu, (int64_t)4 * s.ncu,
+                      (int64_t)8 * s.ncu})
+        if (g >= 1 && g <= full) grids.push_back((int)g);
+    std::sort(grids.begin(), grids.end());
+    grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
+    for (int unroll : {1, 2}) {
+        if (s.coop) {
+            for (int g : grids) {
+                for (int ex : {FCM_EXCHANGE_LEADER, FCM_EXCHANGE_ALLGATHER}) {
+                    if (ex == FCM_EXCHANGE_ALLGATHER && g > kMaxAllGatherGrid) continue;
+                    fcm_tuning t = entry;
+                    t.driver = FCM_DRIVER_PERSISTENT;
+                    t.grid = g;
+                    t.unroll = unroll;
+                    t.exchange = ex;
+                    t.launch = FCM_LAUNCH_RESIDENT;
+                    cand.push_back(t);
+                }
+            }
+        }
+        for (int k : {4, 16}) {
+            fcm_tuning t = entry;
+            t.driver = FCM_DRIVER_GRAPH;
+            t.grid = 0;
+            t.unroll = unroll;
+            t.graph_k = k;
+            cand.push_back(t);
+        }
+    }
+
+    fcm_tuning best = entry;
+    double best_ms = time_single(h, reps, &r);
+    if (best_ms < 0) return FCM_EDEVICE;
+    for (const fcm_tuning& t : cand) {
+        if (fcm_set_tuning(h, &t) != FCM_OK) continue;  // unsupported here
+        fcm_tuning got{};
+        (void)fcm_get_tuning(h, &got);
+        if (t.driver == FCM_DRIVER_PERSISTENT && got.grid != t.grid) continue;  // capped: a duplicate
+        if (fcm_reset(h) != FCM_OK) continue;
+        rc = fcm_solve(h, &r);  // parity check of this configuration, once
+        if ((rc < 0 && rc != FCM_ENUMERIC) || !agrees(r, ref)) continue;
+        const double t_ms = time_single(h, reps, &r);
+        if (t_ms >= 0 && t_ms < best_ms) {
+            best_ms = t_ms;
+            best = got;
+        }
+    }
+    if ((rc = fcm_set_tuning(h, &best)) != FCM_OK) return rc;
+    fcm_tuning fin{};
+    (void)fcm_get_tuning(h, &fin);
+    c.v[0] = fin.driver;
+    c.v[1] = fin.grid;
+    c.v[2] = fin.unroll;
+    c.v[3] = fin.exchange;
+    c.v[4] = fin.launch;
+    c.v[5] = fin.graph_k;
+    c.ms = best_ms;
+    store_choice(cache_path, key.str(), 6, c);
+    if (chosen) *chosen = fin;
+    if (ms) *ms = best_ms;
+    return fcm_reset(h);
+}
+
+int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* chunks_per_thread,
+                       int32_t* grid, double* ms) {
+    if (!b || reps < 1 || reps > 100) return FCM_EINVAL;
+    BatchShape s{};
+    int rc = batch_shape(b, &s);
+    if (rc != FCM_OK) return rc;
+    std::ostringstream key;
+    key << "batch " << device_tag(s.device) << " count=" << s.count << " maxC=" << s.max_C
+        << " vlog2=" << log2_floor(s.voxels);
+    Choice c{};
+    if (load_choice(cache_path, key.str(), 2, &c) && fcm_batch_set_tiling(b, c.v[0], c.v[1]) == FCM_OK) {
+        if (chunks_per_thread) *chunks_per_thread = c.v[0];
+        if (grid) *grid = c.v[1];
+        if (ms) *ms = c.ms;
+        return FCM_OK;
+    }
+    std::vector<fcm_result> ref((size_t)s.count), r((size_t)s.count);
+    rc = fcm_batch_solve(b, ref.data());
+    if (rc < 0 && rc != FCM_ENUMERIC) return rc;
+    int best_cpt = s.chunks_per_thread, best_grid = s.grid;
+    double best_ms = time_batch(b, reps, r);
+    if (best_ms < 0) return FCM_EDEVICE;
+    for (int cpt : {1, 2, 4, 8, 16}) {
+        for (int g : {0, std::max(1, s.max_grid / 2)}) {
+            if (cpt == s.chunks_per_thread && g == s.grid) continue;
+            if (fcm_batch_set_tiling(b, cpt, g) != FCM_OK) continue;
+            rc = fcm_batch_solve(b, r.data());
+            if (rc < 0 && rc != FCM_ENUMERIC) continue;
+            bool ok = true;
+            for (int i = 0; i < s.count && ok; ++i) ok = agrees(r[(size_t)i], ref[(size_t)i]);
+            if (!ok) continue;
+            const double t_ms = time_batch(b, reps, r);
+            if (t_ms >= 0 && t_ms < best_ms) {
+                best_ms = t_ms;
+                best_cpt = cpt;
+                best_grid = g;
+            }
+        }
+    }
+    if ((rc = fcm_batch_set_tiling(b, best_cpt, best_grid)) != FCM_OK) return rc;
+    c.v[0] = best_cpt;
+    c.v[1] = best_grid;
+    c.ms = best_ms;
+    store_choice(cache_path, key.str(), 2, c);
+    if (chunks_per_thread) *chunks_per_thread = best_cpt;
+    if (grid) *grid = best_grid;
+    if (ms) *ms = best_ms;
+    return FCM_OK;
+}
+
+}  // extern "C"

@@ -151,3 +151,10 @@ def test_learned_start_validation(lib):
     r = L.FcmResult()
     assert lib.fcm_solve_warm(None, None, 0, ctypes.byref(r), None, None) == L.FCM_EINVAL
     assert lib.fcm_batch_set_start(None, None, None) == L.FCM_EINVAL
+
+
+def test_autotune_validation(lib):
+    t = L.FcmTuning()
+    ms = ctypes.c_double()
+    assert lib.fcm_autotune(None, None, 3, ctypes.byref(t), ctypes.byref(ms)) == L.FCM_EINVAL
+    assert lib.fcm_batch_autotune(None, None, 2, None, None, None) == L.FCM_EINVAL
