@@ -28,22 +28,8 @@ namespace {
 // round counters compare as signed differences, so they may wrap
 __device__ __forceinline__ bool reached(uint32_t v, uint32_t target) { return (int32_t)(v - target) >= 0; }
 
-__device__ __forceinline__ bool batch_expired(BatchSync* sy, uint64_t t0, uint64_t limit, int& spins) {
-    if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
-    if (wall_clock64() - t0 > limit) {
-        __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return true;
-    }
-    if (spins < 16) {
-        __builtin_amdgcn_s_sleep(1);
-        ++spins;
-    } else {
-        __builtin_amdgcn_s_sleep(8);
-    }
-    return false;
-}
-
-// Wait until the K words at src carry `round` (same scheme as poll_tagged).
+// Wait until the K words at src carry `round` (same scheme as poll_tagged:
+// a few whole-group polls, then the last word with back-off).
 template <int K>
 __device__ __forceinline__ bool batch_poll(const uint64_t* src, uint32_t round, uint32_t (&out)[K], BatchSync* sy,
                                            uint64_t t0, uint64_t limit) {
@@ -57,10 +43,12 @@ __device__ __forceinline__ bool batch_poll(const uint64_t* src, uint32_t round, 
             out[r] = (uint32_t)w;
         }
         if (all) return true;
+        if (poll_expired(sy, t0, limit, spins)) return false;
+        if (spins < kFastPolls) continue;
         while (true) {
-            if (batch_expired(sy, t0, limit, spins)) return false;
             const uint64_t w = __hip_atomic_load(src + K - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((uint32_t)(w >> 32) == round) break;
+            if (poll_expired(sy, t0, limit, spins)) return false;
         }
     }
 }
@@ -103,17 +91,32 @@ __device__ __forceinline__ int read_decision(const uint64_t* dec, uint32_t round
                                              uint64_t limit, float* vn, float* vo, int& p) {
     const uint64_t t0 = wall_clock64();
     int spins = 0;
+    uint32_t raw[kBatchDecWords];
     const uint64_t* ctl = dec + 2 * kMaxC;
     while (true) {
-        const uint64_t w = __hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t tag = (uint32_t)(w >> 32);
-        const uint32_t payload = (uint32_t)w;
-        if ((payload & 1u) && reached(tag, base) && reached(round, tag)) return 0;  // finished earlier in this solve
-        if (tag == round) break;
-        if (batch_expired(sy, t0, limit, spins)) return -1;
+        // a few whole-group polls (one round trip each), then the control
+        // word (written last) with back-off
+        bool all = true;
+        uint32_t ctl_tag = 0;
+#pragma unroll
+        for (int r = 0; r < kBatchDecWords; ++r) {
+            const uint64_t w = __hip_atomic_load(dec + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            all = all && (uint32_t)(w >> 32) == round;
+            raw[r] = (uint32_t)w;
+            ctl_tag = (uint32_t)(w >> 32);  // the last word is the control word
+        }
+        if ((raw[kBatchDecWords - 1] & 1u) && reached(ctl_tag, base) && reached(round, ctl_tag)) return 0;
+        if (all) break;
+        if (poll_expired(sy, t0, limit, spins)) return -1;
+        if (spins < kFastPolls) continue;
+        while (true) {
+            const uint64_t w = __hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t tag = (uint32_t)(w >> 32);
+            if (((uint32_t)w & 1u) && reached(tag, base) && reached(round, tag)) return 0;  // finished earlier
+            if (tag == round) break;
+            if (poll_expired(sy, t0, limit, spins)) return -1;
+        }
     }
-    uint32_t raw[kBatchDecWords];
-    if (!batch_poll<kBatchDecWords>(dec, round, raw, sy, t0, limit)) return -1;
     for (int k = 0; k < kMaxC; ++k) {
         vn[k] = __builtin_bit_cast(float, raw[k]);
         vo[k] = __builtin_bit_cast(float, raw[kMaxC + k]);

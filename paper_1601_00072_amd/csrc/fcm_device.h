@@ -90,10 +90,31 @@ __device__ __forceinline__ float wave_max(float v) {
     return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// FP64 sum over the 64 lanes of a fully active wave, same butterfly as
+// wave_sum.  Each level adds a lane's value and its partner's, which is the
+// same sum in both lanes (addition commutes), so every lane -- and every
+// block holding the same values in the same lanes -- gets identical bits.
 __device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_mov_f64<0xB1>(v);
+    v += dpp_mov_f64<0x4E>(v);
+    v += dpp_mov_f64<0x141>(v);
+    v += dpp_mov_f64<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
@@ -121,6 +142,36 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;
     const float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
+}
+
+// One butterfly level of a compensated (hi, lo) pair sum.  two_sum returns
+// the exact rounding error, so partners compute identical bits.
+template <int CTRL>
+__device__ __forceinline__ void pair_level(float& hi, float& lo) {
+    const float oh = dpp_mov<CTRL>(hi), ol = dpp_mov<CTRL>(lo);
+    float s, e;
+    two_sum(hi, oh, s, e);
+    lo = (lo + ol) + e;
+    hi = s;
+}
+
+// Compensated FP32 sum of (hi, lo) pairs over a fully active wave; the result
+// (identical in every lane) is returned in hi, lo.
+__device__ __forceinline__ void wave_sum_pair(float& hi, float& lo) {
+    pair_level<0xB1>(hi, lo);
+    pair_level<0x4E>(hi, lo);
+    pair_level<0x141>(hi, lo);
+    pair_level<0x140>(hi, lo);
+    float h = readlane_f(hi, 0), l = readlane_f(lo, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) {
+        float s, e;
+        two_sum(h, readlane_f(hi, r), s, e);
+        l = (l + readlane_f(lo, r)) + e;
+        h = s;
+    }
+    hi = h;
+    lo = l;
 }
 
 template <typename T>
@@ -169,28 +220,45 @@ __device__ __forceinline__ void store_tagged(uint64_t* p, uint32_t round, uint32
     __hip_atomic_store(p, tagged(round, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// one poll step's bookkeeping (sleep with backoff); true when the caller must
-// give up
+// one poll step's bookkeeping; true when the caller must give up.  The wall
+// clock is read every step, the shared abort word only every 32nd (it costs a
+// memory round trip); short sleeps first, longer ones once the wait drags on.
 __device__ __forceinline__ bool poll_expired(SyncState* sy, uint64_t t0, uint64_t limit_ticks, int& spins) {
-    if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
     if (wall_clock64() - t0 > limit_ticks) {
         __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     }
-    if (spins < 16) {
+    if ((spins & 31) == 31 && __hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    ++spins;
+    if (spins < 64)
         __builtin_amdgcn_s_sleep(1);
-        ++spins;
-    } else {
+    else
         __builtin_amdgcn_s_sleep(8);
-    }
     return false;
 }
 
-// Wait until the K words at src carry `round`; payloads into out.  The whole
-// group is read once; while it is incomplete only its last word is watched
-// (the writer stores it last), then the group is read again.  A reader that
-// arrives after the writer needs one round trip; waiting readers generate one
-// load per poll.
+__device__ __forceinline__ bool poll_expired(BatchSync* sy, uint64_t t0, uint64_t limit_ticks, int& spins) {
+    if (wall_clock64() - t0 > limit_ticks) {
+        __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    if ((spins & 31) == 31 && __hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    ++spins;
+    if (spins < 64)
+        __builtin_amdgcn_s_sleep(1);
+    else
+        __builtin_amdgcn_s_sleep(8);
+    return false;
+}
+
+// Wait until the K words at src carry `round`; payloads into out.  A short
+// wait re-reads the whole group (its words are issued back to back, so a poll
+// costs one memory round trip); once the wait drags on, only the group's last
+// word (stored last by the writer) is watched, with back-off, and the group
+// is read again when it arrives -- this bounds the load traffic when many
+// blocks wait on many rows (a large all-gather grid).
+constexpr int kFastPolls = 4;
+
 template <int K>
 __device__ __forceinline__ bool poll_tagged(const uint64_t* src, uint32_t round, uint32_t (&out)[K], SyncState* sy,
                                             uint64_t t0, uint64_t limit_ticks) {
@@ -204,10 +272,12 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, uint32_t round,
             out[r] = (uint32_t)w;
         }
         if (all) return true;
+        if (poll_expired(sy, t0, limit_ticks, spins)) return false;
+        if (spins < kFastPolls) continue;
         while (true) {
-            if (poll_expired(sy, t0, limit_ticks, spins)) return false;
             const uint64_t w = __hip_atomic_load(src + K - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((uint32_t)(w >> 32) == round) break;
+            if (poll_expired(sy, t0, limit_ticks, spins)) return false;
         }
     }
 }
@@ -234,26 +304,28 @@ struct PlainRows {
     }
 };
 
-// Row-major tagged rows [G][K], K = 2C + 2 (cooperative launch).  Each pair is
-// folded to one FP32 value (sum - comp, within half an ulp) so that a row is
-// K self-validating words; a reader polls the whole row in one round trip.
+// Row-major tagged rows [G][stride], K = 2C + 2 words used (persistent
+// launch).  Each pair is folded to one FP32 value (sum - comp, within half an
+// ulp) so that a row is K self-validating words; a reader polls the whole row
+// in one round trip.
 template <int K>
 struct TaggedRows {
+    static constexpr int S = tagged_stride(K);
     uint64_t* W;
     uint32_t round;
     SyncState* sy;
     uint64_t t0, limit;
     __device__ __forceinline__ void put_pair(int q, float s, float c) const {
-        store_tagged(W + (size_t)blockIdx.x * K + q, round, __builtin_bit_cast(uint32_t, s - c));
+        store_tagged(W + (size_t)blockIdx.x * S + q, round, __builtin_bit_cast(uint32_t, s - c));
     }
     __device__ __forceinline__ void put_max(int q, float m) const {
-        store_tagged(W + (size_t)blockIdx.x * K + q, round, __builtin_bit_cast(uint32_t, m));
+        store_tagged(W + (size_t)blockIdx.x * S + q, round, __builtin_bit_cast(uint32_t, m));
     }
     template <int R>
     __device__ __forceinline__ bool get(int b, float (&v)[R]) const {
         static_assert(R == 2 * (K - 1) + 1, "row format");
         uint32_t raw[K];
-        if (!poll_tagged<K>(W + (size_t)b * K, round, raw, sy, t0, limit)) return false;
+        if (!poll_tagged<K>(W + (size_t)b * S, round, raw, sy, t0, limit)) return false;
 #pragma unroll
         for (int q = 0; q < K - 1; ++q) {
             v[2 * q] = __builtin_bit_cast(float, raw[q]);
@@ -688,16 +760,7 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
     } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            for (int off = 1; off < 64; off <<= 1) {
-                const float oh = __shfl_xor(hi[q], off, 64);
-                const float ol = __shfl_xor(lo[q], off, 64);
-                float s, e;
-                // order the operands so both lanes of a pair compute the same bits
-                const bool low = (lane & off) == 0;
-                two_sum(low ? hi[q] : oh, low ? oh : hi[q], s, e);
-                lo[q] = (low ? lo[q] + ol : ol + lo[q]) + e;
-                hi[q] = s;
-            }
+            wave_sum_pair(hi[q], lo[q]);
             if (lane == 0) {
                 s_sum[wid][q] = (double)hi[q];
                 s_lo[wid][q] = lo[q];
@@ -1064,7 +1127,7 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
         run_pass<C, MK, UNROLL>(a, p, vn, vo, acc, resident, mine);
         ++round;
         constexpr int K = 2 * C + 2;
-        const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * K * G, round, sy, (uint64_t)wall_clock64(),
+        const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * TaggedRows<K>::S * G, round, sy, (uint64_t)wall_clock64(),
                                  a.spin_ticks};
         write_partial_row<C>(acc, rows);
         if (leader || a.allgather) {

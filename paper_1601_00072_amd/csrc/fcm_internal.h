@@ -45,6 +45,13 @@ struct DevState {
 // then delta (max).  Row count 4C + 3.
 __host__ __device__ constexpr int partial_rows(int C) { return 4 * C + 3; }
 
+// Row stride (64-bit words) of a persistent launch's tagged row of K words:
+// rows start on 128-byte boundaries, so a row of up to 16 words is one cache
+// line.  Buffer: [2][kMaxPersistGrid][kTaggedStrideMax] words.
+__host__ __device__ constexpr int tagged_stride(int K) { return K <= 16 ? 16 : 32; }
+constexpr int kTaggedStrideMax = 32;
+static_assert(tagged_stride(2 * kMaxC + 2) <= kTaggedStrideMax, "tagged row buffer too small");
+
 enum MClass : int { kM2 = 0, kM15 = 1, kMGeneric = 2 };
 
 struct PassArgs {
@@ -63,7 +70,7 @@ struct PassArgs {
     int32_t max_iter;
     int32_t kahan_only;    // cross-block reduction in compensated FP32
     // cooperative driver only
-    uint64_t* rows;        // [2][grid][rows] tagged partial rows, by round parity
+    uint64_t* rows;        // [2][grid][16 or 32] tagged partial rows, by round parity
     uint64_t* mm_rows;     // [2][grid][2] tagged per-block grey-level range, by round parity
     int32_t allgather;     // every block reduces all rows (else block 0 reduces and broadcasts)
     int32_t pad2;
@@ -100,7 +107,7 @@ struct LabelArgs {
 
 // ---- batched solver: many instances of uneven size in one cooperative launch ----
 
-constexpr int kBatchRowWords = 2 * kMaxC + 2;  // tagged words per tile row (stride for any C)
+constexpr int kBatchRowWords = 32;  // stride of a tile row (2C + 2 tagged words used), 256-byte aligned
 constexpr int kBatchDecWords = 2 * kMaxC + 1;  // tagged decision words per instance
 
 struct BatchInst {

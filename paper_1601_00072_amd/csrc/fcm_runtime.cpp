@@ -332,7 +332,7 @@ int run_batch(fcm_handle* h, int batch) {
 int enqueue_start(fcm_handle* h) {
     if (h->aborted) {
         FCM_HIP(hipMemsetAsync(h->d_state, 0, sizeof(DevState), h->stream));
-        FCM_HIP(hipMemsetAsync(h->d_rows, 0, sizeof(uint64_t) * 2 * kMaxPersistGrid * partial_rows(kMaxC), h->stream));
+        FCM_HIP(hipMemsetAsync(h->d_rows, 0, sizeof(uint64_t) * 2 * kMaxPersistGrid * kTaggedStrideMax, h->stream));
         FCM_HIP(hipMemsetAsync(h->d_mmrows, 0, sizeof(uint64_t) * 4 * kMaxPersistGrid, h->stream));
         h->aborted = false;
     } else {
@@ -441,7 +441,7 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     if (hipMalloc(&h->d_partials, sizeof(float) * partial_rows(kMaxC) * kMaxGrid) != hipSuccess)
         return fail(FCM_ENOMEM);
     if (hipMalloc(&h->d_minmax, sizeof(uint32_t) * 2 * kMaxGrid) != hipSuccess) return fail(FCM_ENOMEM);
-    if (hipMalloc(&h->d_rows, sizeof(uint64_t) * 2 * kMaxPersistGrid * partial_rows(kMaxC)) != hipSuccess)
+    if (hipMalloc(&h->d_rows, sizeof(uint64_t) * 2 * kMaxPersistGrid * kTaggedStrideMax) != hipSuccess)
         return fail(FCM_ENOMEM);
     if (hipMalloc(&h->d_mmrows, sizeof(uint64_t) * 4 * kMaxPersistGrid) != hipSuccess) return fail(FCM_ENOMEM);
     const size_t hist_doubles = (size_t)(p->max_iter + 2) * (C + 2);
