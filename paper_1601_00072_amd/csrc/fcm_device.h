@@ -53,6 +53,7 @@
 
 #include "fcm.h"
 #include "fcm_internal.h"
+#include "fcm_learn_dev.h"
 
 namespace fcm {
 
@@ -894,8 +895,10 @@ __global__ __launch_bounds__(kBlock) void fcm_pass_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 
 // min and max grey level of this thread's voxels (grid-stride chunks + ragged)
+// Grey-level range of this thread's voxels; with `bins` (a shared 256-entry
+// table) also their histogram.
 __device__ __forceinline__ void thread_minmax(const uint8_t* x, int64_t n, int64_t head, int64_t nbody,
-                                              uint32_t& lo, uint32_t& hi) {
+                                              uint32_t& lo, uint32_t& hi, uint32_t* bins = nullptr) {
     const int tid = threadIdx.x;
     const uint4* body = reinterpret_cast<const uint4*>(x + head);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -909,6 +912,7 @@ __device__ __forceinline__ void thread_minmax(const uint8_t* x, int64_t n, int64
                 const uint32_t v = (words[i] >> (8 * b)) & 0xFFu;
                 lo = min(lo, v);
                 hi = max(hi, v);
+                if (bins) atomicAdd(bins + v, 1u);
             }
         }
     }
@@ -919,6 +923,7 @@ __device__ __forceinline__ void thread_minmax(const uint8_t* x, int64_t n, int64
             const int64_t i = tid < head ? (int64_t)tid : tail0 + (tid - head);
             lo = min(lo, (uint32_t)x[i]);
             hi = max(hi, (uint32_t)x[i]);
+            if (bins) atomicAdd(bins + x[i], 1u);
         }
     }
 }
@@ -1046,12 +1051,40 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
     uint32_t round = __hip_atomic_load(&sy->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     if (a.do_init) {
+        // learned start: the data-range pass also counts the grey levels
+        // (shared table per block, then global counters), and block 0 runs
+        // the network on the histogram before the first pass
+        const bool learned = a.given == 3;
+        __shared__ uint32_t s_bins[kWaves][256];  // one table per wave: fewer same-address conflicts
+        if (learned) {
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s_bins[w][tid] = 0u;
+            __syncthreads();
+        }
         uint32_t lo = 255u, hi = 0u;
-        thread_minmax(a.x, a.n, a.head, a.nbody, lo, hi);
+        thread_minmax(a.x, a.n, a.head, a.nbody, lo, hi, learned ? s_bins[tid >> 6] : nullptr);
         block_minmax(lo, hi);
+        if (learned) {
+            __syncthreads();
+            uint32_t c = 0u;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) c += s_bins[w][tid];
+            // block b adds into copy b mod kHistCopies, so that a busy grey
+            // level sees kHistCopies times fewer same-address atomics.  The
+            // returned value is consumed so that the wave waits until its add
+            // has been performed before the barrier.
+            if (c) {
+                const uint32_t old = __hip_atomic_fetch_add(a.ghist + (blockIdx.x % kHistCopies) * 256 + tid, c,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                asm volatile("" ::"v"(old));
+            }
+            __syncthreads();
+        }
         ++round;
         uint64_t* mm = a.mm_rows + (size_t)(round & 1u) * 2 * G;
         if (tid == 0) {
+            // the block's counts are released before its range row
+            if (learned) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             store_tagged(mm + 2 * blockIdx.x, round, lo);
             store_tagged(mm + 2 * blockIdx.x + 1, round, hi);
         }
@@ -1065,9 +1098,41 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 return true;
             };
             if (!reduce_minmax(get, G, lo, hi)) return;
+            __shared__ double s_w0[kMaxC];
+            if (learned) {
+                // every block whose range row was seen released its counts
+                // first.  With all-gather every block runs the network itself
+                // on the same counts (same code, same result: no broadcast);
+                // otherwise block 0 does and broadcasts the start.
+                __shared__ float s_h[256], s_a0[256], s_a1[128], s_a2[64], s_tmp[256], s_y[kMaxC];
+                // The counters are read with device-scope atomic loads, which
+                // are served at the same coherence point where the adds were
+                // performed; each writer's adds had completed (their results
+                // were consumed) before its release fence and range row, and
+                // these loads are issued only after the barrier that follows
+                // the polls that saw every range row.  An acquire fence here
+                // would add nothing for atomic loads but cost ~5 us (an L2
+                // invalidation in every wave).
+                uint32_t part[kHistCopies];
+#pragma unroll
+                for (int c = 0; c < kHistCopies; ++c)
+                    part[c] = __hip_atomic_load(a.ghist + c * 256 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t cnt = 0u;
+#pragma unroll
+                for (int c = 0; c < kHistCopies; ++c) cnt += part[c];
+                // the counters of the next learned launch (the other buffer)
+                // start at zero: no block of this launch touches them
+                if (leader)
+                    for (int c = 0; c < kHistCopies; ++c) a.ghist_next[c * 256 + tid] = 0u;
+                s_h[tid] = hist_norm(cnt, a.n);
+                __syncthreads();
+                mlp_block_forward<true>(a.mlp_w, s_h, C, s_a0, s_a1, s_a2, s_tmp, s_y);
+                __syncthreads();
+                if (tid == 0) warm_post_one(s_y, (int)lo, (int)hi, C, s_w0);
+            }
             if (tid == 0) {
                 double v[C];
-                start_centroids(C, lo, hi, a.given, a.v0, a.dv0, v);
+                start_centroids(C, lo, hi, learned ? 2 : a.given, a.v0, learned ? s_w0 : a.dv0, v);
                 for (int k = 0; k < C; ++k) {
                     s_v64[k] = v[k];
                     s_vn[k] = (float)v[k];
@@ -1084,7 +1149,10 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 int p = 0, done = 0;
                 s_ok = await_decision<C>(sy, round, a.spin_ticks, v, p, done);
 #pragma unroll
-                for (int k = 0; k < C; ++k) s_vn[k] = s_vo[k] = v[k];
+                for (int k = 0; k < C; ++k) {
+                    s_vn[k] = s_vo[k] = v[k];
+                    s_v64[k] = (double)v[k];  // v^0 is FP32-exact
+                }
                 s_p = p;
                 s_done = done;
             }

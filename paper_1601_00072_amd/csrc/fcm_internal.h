@@ -75,13 +75,19 @@ struct PassArgs {
     int32_t allgather;     // every block reduces all rows (else block 0 reduces and broadcasts)
     int32_t pad2;
     int32_t do_init;       // run the data-range pass and set v^0 first
-    int32_t given;         // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device)
+    int32_t given;         // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device),
+                           // 3 learned (persistent launch only; mlp_w, ghist below)
     double v0[kMaxC];
     const double* dv0;     // C start centroids in device memory (mode 2)
     int32_t max_passes;    // passes this launch may run
     int32_t pad;
     uint64_t spin_ticks;   // wall-clock limit of one wait
+    const uint16_t* mlp_w; // mode 3: BF16 parameters of the histogram -> centroid network (C outputs)
+    uint32_t* ghist;       // mode 3: [kHistCopies][256] grey-level counters, zero at entry
+    uint32_t* ghist_next;  // mode 3: the counters of the next learned launch, zeroed by this one
 };
+
+constexpr int kHistCopies = 16;  // copies of the in-kernel histogram (blocks spread their atomics)
 
 struct InitArgs {
     const uint8_t* x;

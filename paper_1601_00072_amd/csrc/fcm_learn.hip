@@ -13,6 +13,7 @@
 
 #include "fcm_internal.h"
 #include "fcm_learn.h"
+#include "fcm_learn_dev.h"
 
 namespace fcm {
 
@@ -57,9 +58,8 @@ __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint8_t* x, co
 __global__ __launch_bounds__(kBlock) void hist_norm_kernel(const uint32_t* counts, const int64_t* offsets,
                                                            float* hist) {
     const int inst = blockIdx.x;
-    const double n = (double)(offsets[inst + 1] - offsets[inst]);
     const int64_t o = (int64_t)inst * 256 + threadIdx.x;
-    hist[o] = (float)((double)counts[o] / n);
+    hist[o] = hist_norm(counts[o], offsets[inst + 1] - offsets[inst]);
 }
 
 hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
@@ -229,88 +229,50 @@ hipError_t launch_gather(const float* X, const int32_t* idx, int rows, int cols,
 // BF16 inference
 // ---------------------------------------------------------------------------
 
-// round to nearest even; NaN stays NaN
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// BF16 inference copy (InferLayout) of the flat FP32 parameters, one thread
+// per element of the copy.
+__global__ void to_bf16_kernel(const float* theta, uint16_t* out, int C) {
+    using L = InferLayout;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t fW1 = 0, fb1 = fW1 + 256 * 128, fW2 = fb1 + 128, fb2 = fW2 + 128 * 64, fW3 = fb2 + 64;
+    const int64_t fb3 = fW3 + 64 * (int64_t)C;
+    int64_t src;
+    if (e < L::b1) src = fW1 + (e % 256) * 128 + e / 256;                      // W1t[o][i] = W1[i][o]
+    else if (e < L::W2) src = fb1 + (e - L::b1);
+    else if (e < L::b2) src = fW2 + ((e - L::W2) % 128) * 64 + (e - L::W2) / 128;
+    else if (e < L::W3) src = fb2 + (e - L::b2);
+    else if (e < L::b3(C)) src = fW3 + ((e - L::W3) % 64) * C + (e - L::W3) / 64;
+    else if (e < L::b3(C) + C) src = fb3 + (e - L::b3(C));
+    else return;
+    out[e] = to_bf16(theta[src]);
 }
 
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
-
-__global__ void to_bf16_kernel(const float* in, uint16_t* out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = to_bf16(in[i]);
-}
-
-hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+hipError_t launch_to_bf16(const float* theta, uint16_t* out, int C, hipStream_t s) {
+    const int64_t n = InferLayout::b3(C) + C;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, out, C);
     return hipGetLastError();
 }
 
-// One block (128 threads) per histogram: the three layers in a fixed order of
-// summation, FP32 accumulation.  BF16: weights and activations (the input
-// histogram included) rounded to BF16 before every product; otherwise FP32
-// weights and activations.  Output y[C] in FP32.
+// One block (256 threads) per histogram (mlp_block_forward).
 template <bool BF16>
-__device__ __forceinline__ float wload(const void* w, int64_t i) {
-    if constexpr (BF16)
-        return from_bf16(static_cast<const uint16_t*>(w)[i]);
-    else
-        return static_cast<const float*>(w)[i];
-}
-
-template <bool BF16>
-__device__ __forceinline__ float act(float v) {
-    if constexpr (BF16)
-        return from_bf16(to_bf16(v));
-    else
-        return v;
-}
-
-template <bool BF16>
-__global__ __launch_bounds__(128) void mlp_infer_kernel(const void* w, const float* X, int C, float* Y) {
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const void* w, const float* X, int C, float* Y) {
     __shared__ float a0[256];
     __shared__ float a1[128];
     __shared__ float a2[64];
-    const int s = blockIdx.x, t = threadIdx.x;
-    constexpr int64_t oW1 = 0, ob1 = oW1 + 256 * 128, oW2 = ob1 + 128, ob2 = oW2 + 128 * 64, oW3 = ob2 + 64;
-    const int64_t ob3 = oW3 + 64 * (int64_t)C;
-    for (int i = t; i < 256; i += 128) a0[i] = act<BF16>(X[(int64_t)s * 256 + i]);
-    __syncthreads();
-    {
-        float z = wload<BF16>(w, ob1 + t);
-        for (int i = 0; i < 256; ++i) z = fmaf(a0[i], wload<BF16>(w, oW1 + i * 128 + t), z);
-        a1[t] = act<BF16>(fmaxf(z, 0.f));
-    }
-    __syncthreads();
-    if (t < 64) {
-        float z = wload<BF16>(w, ob2 + t);
-        for (int i = 0; i < 128; ++i) z = fmaf(a1[i], wload<BF16>(w, oW2 + i * 64 + t), z);
-        a2[t] = act<BF16>(fmaxf(z, 0.f));
-    }
-    __syncthreads();
-    if (t < C) {
-        float z = wload<BF16>(w, ob3 + t);
-        for (int i = 0; i < 64; ++i) z = fmaf(a2[i], wload<BF16>(w, oW3 + i * C + t), z);
-        Y[(int64_t)s * C + t] = z;
-    }
+    __shared__ float tmp[256];
+    const int64_t s = blockIdx.x;
+    mlp_block_forward<BF16>(w, X + s * 256, C, a0, a1, a2, tmp, Y + s * C);
 }
 
 hipError_t launch_mlp_infer(const void* w, bool bf16, const float* X, int count, int C, float* Y, hipStream_t s) {
     if (bf16)
-        hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(count), dim3(128), 0, s, w, X, C, Y);
+        hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(count), dim3(256), 0, s, w, X, C, Y);
     else
-        hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(count), dim3(128), 0, s, w, X, C, Y);
+        hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(count), dim3(256), 0, s, w, X, C, Y);
     return hipGetLastError();
 }
 
-// Network output -> starting centroids, one thread per instance: v = 255 y,
-// sorted ascending, clamped to the data range [lo, hi] read off the histogram,
-// consecutive gaps of at least 1; written as C doubles (FP32 values), or NaN
-// when no valid set exists (non-finite output, or hi - lo < C - 1), which makes
-// the solve fall back to evenly spaced centroids.
+// Network output -> start centroids, one thread per instance (warm_post_one).
 __global__ void warm_post_kernel(const float* Y, const float* hist, int count, int C, double* v0) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
@@ -318,29 +280,7 @@ __global__ void warm_post_kernel(const float* Y, const float* hist, int count, i
     int lo = 0, hi = 255;
     while (lo < 255 && !(h[lo] > 0.f)) ++lo;
     while (hi > 0 && !(h[hi] > 0.f)) --hi;
-    float v[kMaxC];
-    bool ok = hi - lo >= C - 1;
-    for (int k = 0; k < C; ++k) {
-        v[k] = 255.f * Y[(int64_t)s * C + k];
-        if (!isfinite(v[k])) ok = false;
-    }
-    for (int k = 1; k < C; ++k) {  // insertion sort
-        const float key = v[k];
-        int j = k - 1;
-        while (j >= 0 && v[j] > key) {
-            v[j + 1] = v[j];
-            --j;
-        }
-        v[j + 1] = key;
-    }
-    for (int k = 0; k < C; ++k) v[k] = fminf(fmaxf(v[k], (float)lo), (float)hi);
-    for (int k = 1; k < C; ++k) v[k] = fmaxf(v[k], v[k - 1] + 1.f);
-    if (v[C - 1] > (float)hi) {  // push back from the top
-        v[C - 1] = (float)hi;
-        for (int k = C - 2; k >= 0; --k) v[k] = fminf(v[k], v[k + 1] - 1.f);
-        if (v[0] < (float)lo) ok = false;
-    }
-    for (int k = 0; k < C; ++k) v0[(int64_t)s * C + k] = ok ? (double)v[k] : __builtin_nan("");
+    warm_post_one(Y + (int64_t)s * C, lo, hi, C, v0 + (int64_t)s * C);
 }
 
 hipError_t launch_warm_post(const float* Y, const float* hist, int count, int C, double* v0, hipStream_t s) {

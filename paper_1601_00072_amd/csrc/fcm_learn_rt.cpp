@@ -172,7 +172,7 @@ int backward(fcm_mlp* n, int rows, float* loss_slot) {
 int refresh_bf16(fcm_mlp* n, hipStream_t s) {
     if (!n->wb_stale) return FCM_OK;
     if (s != n->stream) FCM_HIP(hipStreamSynchronize(n->stream));
-    FCM_HIP(launch_to_bf16(n->theta, n->wb, n->P, s));
+    FCM_HIP(launch_to_bf16(n->theta, n->wb, n->C, s));
     if (s != n->stream) FCM_HIP(hipStreamSynchronize(s));
     n->wb_stale = false;
     return FCM_OK;
@@ -183,6 +183,11 @@ int refresh_bf16(fcm_mlp* n, hipStream_t s) {
 namespace fcm {
 
 int mlp_clusters(const fcm_mlp* net) { return net ? net->C : 0; }
+
+const uint16_t* mlp_bf16_weights(fcm_mlp* net, hipStream_t s, int* rc) {
+    *rc = refresh_bf16(net, s);
+    return net->wb;
+}
 
 int mlp_warm(fcm_mlp* net, const float* d_hist, int count, float* d_y, double* d_v0, hipStream_t s) {
     int rc = refresh_bf16(net, s);

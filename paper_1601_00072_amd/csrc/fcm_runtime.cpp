@@ -122,6 +122,10 @@ struct fcm_handle {
     float* d_whist = nullptr;      // [256]
     float* d_wy = nullptr;         // [kMaxC] network output
     double* d_wv0 = nullptr;       // [kMaxC] learned start
+    uint32_t* d_ghist = nullptr;   // [2][kHistCopies][256] counters of the in-kernel histogram; a learned
+                                   // launch uses buffer ghist_sel and zeroes the other one
+    uint32_t ghist_sel = 0;
+    const uint16_t* mlp_w = nullptr;  // BF16 network of the running fused warm solve
 
     double* hist_v() const { return d_hist; }
     double* hist_d() const { return d_hist + (int64_t)(p.max_iter + 2) * p.n_clusters; }
@@ -132,7 +136,13 @@ namespace {
 
 int64_t chunk_blocks(const fcm_handle* h) { return (h->nbody + kBlock - 1) / kBlock; }
 
-int start_mode(int init) { return init == FCM_INIT_GIVEN ? 1 : (init == FCM_INIT_DEVICE ? 2 : 0); }
+// Internal start mode of a warm solve on the persistent driver: histogram and
+// network inference inside the solve kernel.
+constexpr int32_t kInitLearnedFused = 0x100;
+
+int start_mode(int init) {
+    return init == FCM_INIT_GIVEN ? 1 : (init == FCM_INIT_DEVICE ? 2 : (init == kInitLearnedFused ? 3 : 0));
+}
 
 int resolve_grid(fcm_handle* h, int* out) {
     int64_t want = h->tun.grid > 0 ? h->tun.grid : std::min<int64_t>(chunk_blocks(h), 4LL * h->ncu);
@@ -171,6 +181,9 @@ PassArgs pass_args(const fcm_handle* h) {
     a.given = start_mode(h->p.init);
     for (int k = 0; k < kMaxC; ++k) a.v0[k] = h->given[k];
     a.dv0 = h->dv0;
+    a.mlp_w = h->mlp_w;
+    a.ghist = h->d_ghist ? h->d_ghist + (size_t)(h->ghist_sel & 1) * 256 * kHistCopies : nullptr;
+    a.ghist_next = h->d_ghist ? h->d_ghist + (size_t)((h->ghist_sel + 1) & 1) * 256 * kHistCopies : nullptr;
     a.max_passes = 0;
     a.spin_ticks = h->spin_ticks;
     return a;
@@ -334,6 +347,7 @@ int enqueue_start(fcm_handle* h) {
         FCM_HIP(hipMemsetAsync(h->d_state, 0, sizeof(DevState), h->stream));
         FCM_HIP(hipMemsetAsync(h->d_rows, 0, sizeof(uint64_t) * 2 * kMaxPersistGrid * kTaggedStrideMax, h->stream));
         FCM_HIP(hipMemsetAsync(h->d_mmrows, 0, sizeof(uint64_t) * 4 * kMaxPersistGrid, h->stream));
+        if (h->d_ghist) FCM_HIP(hipMemsetAsync(h->d_ghist, 0, sizeof(uint32_t) * 2 * 256 * kHistCopies, h->stream));
         h->aborted = false;
     } else {
         FCM_HIP(hipMemsetAsync(h->d_state, 0, offsetof(DevState, sync), h->stream));
@@ -364,7 +378,8 @@ void release(fcm_handle* h) {
     if (h->d_rows) (void)hipFree(h->d_rows);
     if (h->d_mmrows) (void)hipFree(h->d_mmrows);
     if (h->d_hist) (void)hipFree(h->d_hist);
-    for (void* p : {(void*)h->d_woff, (void*)h->d_wcounts, (void*)h->d_whist, (void*)h->d_wy, (void*)h->d_wv0})
+    for (void* p : {(void*)h->d_woff, (void*)h->d_wcounts, (void*)h->d_whist, (void*)h->d_wy, (void*)h->d_wv0,
+                    (void*)h->d_ghist})
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
     delete h;
@@ -542,17 +557,33 @@ int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, 
         if ((rc = enqueue_start(h)) != FCM_OK) return rc;
         if ((rc = fcm_solve(h, &rp)) < 0) return rc;
     }
-    // learned start: histogram -> network (BF16) -> start centroids, then Algorithm 1
-    FCM_HIP(launch_histogram(h->d_x, h->d_woff, 1, h->n, h->d_wcounts, h->d_whist, h->stream));
-    if ((rc = mlp_warm(net, h->d_whist, 1, h->d_wy, h->d_wv0, h->stream)) != FCM_OK) return rc;
+    // learned start: histogram -> network (BF16) -> start centroids, then
+    // Algorithm 1.  The persistent driver does all of it in its one launch
+    // (the data-range pass counts the grey levels, block 0 runs the network);
+    // the other drivers launch the histogram and network kernels first.  Both
+    // ways run the same device code and give the same start.
     const int32_t own_init = h->p.init;
     const double* own_dv0 = h->dv0;
-    h->p.init = FCM_INIT_DEVICE;
-    h->dv0 = h->d_wv0;
+    if (h->tun.driver == FCM_DRIVER_PERSISTENT) {
+        if (!h->d_ghist) {
+            if (hipMalloc(&h->d_ghist, sizeof(uint32_t) * 2 * 256 * kHistCopies) != hipSuccess) return FCM_ENOMEM;
+            FCM_HIP(hipMemsetAsync(h->d_ghist, 0, sizeof(uint32_t) * 2 * 256 * kHistCopies, h->stream));
+        }
+        h->mlp_w = mlp_bf16_weights(net, h->stream, &rc);
+        if (rc != FCM_OK) return rc;
+        h->p.init = kInitLearnedFused;
+    } else {
+        FCM_HIP(launch_histogram(h->d_x, h->d_woff, 1, h->n, h->d_wcounts, h->d_whist, h->stream));
+        if ((rc = mlp_warm(net, h->d_whist, 1, h->d_wy, h->d_wv0, h->stream)) != FCM_OK) return rc;
+        h->p.init = FCM_INIT_DEVICE;
+        h->dv0 = h->d_wv0;
+    }
     rc = enqueue_start(h);
     if (rc == FCM_OK) rc = fcm_solve(h, &rw);
+    if (h->p.init == kInitLearnedFused && rc >= 0) h->ghist_sel ^= 1u;  // that launch zeroed the other buffer
     h->p.init = own_init;
     h->dv0 = own_dv0;
+    h->mlp_w = nullptr;
     if (rc < 0) return rc;
     int use = 1;
     if (check) {

@@ -300,3 +300,40 @@ def test_trained_network_gain(torch_dev):
     assert losses[-1] < 0.1 * losses[0]
     assert ev["iters_warm_mean"] < ev["iters_plain_mean"]
     assert ev["max_rel_J_excess_accepted"] <= 1e-6
+
+
+@pytest.mark.parametrize("shape,driver", [((64, 128, 128), 2), ((64, 128, 128), 1), ((173, 211), 2)])
+def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver):
+    """The persistent driver computes the histogram and runs the network inside
+    its one launch; the graph driver launches the histogram and network
+    kernels first.  Both must start from the start the oracle derives (FP64
+    BF16 forward + the post-processing rule) and then follow the FP64 oracle."""
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCM, MLP
+    from tests import _parity as P
+    announce("warm start", shape, "driver", driver)
+    x = phantom(PhantomParams(shape=shape, seed=17)).ravel()
+    xt = torch.from_numpy(x).to(d)
+    h = fcm_hist.histogram(x)
+    hn = (h / x.size).astype(np.float32).astype(np.float64)
+    with MLP(4, seed=3) as net:
+        theta = net.params().astype(np.float64)
+        y = mlp_ref.forward_bf16(theta, hn[None, :], 4)[0]
+        with FCM(xt, 4) as f:
+            f.set_tuning(driver=driver)
+            res, used, _ = f.solve_warm(net, check=False)
+            traj = P.gpu_trajectory(f, res.iters)
+            lab = f.labels().cpu().numpy()
+    v0 = post_reference(y.astype(np.float32), hn, 4)
+    assert np.all(np.isfinite(v0))
+    v0 = v0.astype(np.float32).astype(np.float64)
+    # the BF16 kernel accumulates in FP32: its output can differ from the FP64
+    # oracle's by a few FP32 ulp (and one BF16 step where a boundary is crossed)
+    assert np.max(np.abs(traj[0][0] - v0)) <= 0.05, (traj[0][0], v0)
+    ora = fcm_hist.solve(h, 4, 2.0, 1e-5, 300, v0=v0)
+    if res.iters != ora.T:
+        ext = fcm_hist.solve(h, 4, 2.0, 0.0, max(res.iters, ora.T) + 1, v0=ora.v[0])
+        P.check_iterations(res, ora.T, ext, 1e-5, hist=h, m=2.0, gpu_vs=traj[0])
+        ora = ext
+    P.compare(res, traj, ora, 1e-5, hist=h, m=2.0)
+    P.check_labels(x, lab, ora.v[res.iters])
