@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--launch", choices=("cooperative", "resident"), default="resident",
                     help="launch of the persistent solve kernel")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache file (a matching entry is applied without timing)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 5 times (counter calibration)")
     return ap.parse_args()
@@ -132,15 +134,16 @@ def timed_solves(f, steps, labels=None):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fcm_persist_kernel_volume_1M_c4_m2.md")
+TUNE_CACHE = os.path.join(ROOT, "paper_1601_00072_amd", "tuning_mi355x.txt")
 
 
 def sources_digest() -> str:
-    """SHA-256 prefix over the library's kernel and runtime sources."""
+    """SHA-256 prefix over the library's device sources (.hip, .h)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1601_00072_amd", "csrc")
     for name in sorted(os.listdir(src)):
-        if name.endswith((".hip", ".h", ".cpp")):
+        if name.endswith((".hip", ".h")):
             h.update(name.encode())
             h.update(b"\0")
             with open(os.path.join(src, name), "rb") as fh:
@@ -148,9 +151,14 @@ def sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(shape, C, m):
+def tuning_tag(t) -> str:
+    return f"grid={t['grid']},unroll={t['unroll']},exchange={t['exchange']},launch={t['launch']}"
+
+
+def recorded_traffic(shape, C, m, tuning):
     """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary, or None when it was taken on other sources or another workload."""
+    summary, or None when it was taken on other device sources, another
+    workload or another launch configuration."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
             for line in fh:
@@ -158,6 +166,7 @@ def recorded_traffic(shape, C, m):
                 if f[:1] == ["traffic_bytes_per_launch:"]:
                     kv = dict(zip(f[0::2], f[1::2]))
                     same = (kv.get("sources_digest:") == sources_digest()
+                            and kv.get("tuning:") == tuning_tag(tuning)
                             and kv.get("workload:") == ",".join(map(str, shape))
                             and f"C={C}" in f and f"m={float(m)}" in f)
                     return int(kv["traffic_bytes_per_launch:"]) if same else None
@@ -172,7 +181,7 @@ def roofline(n, C, m, passes_per_launch, launch_s):
     return achieved
 
 
-def large_volume(dev):
+def large_volume(dev, tune_cache):
     import torch
 
     from paper_1601_00072_amd import FCM
@@ -181,7 +190,7 @@ def large_volume(dev):
     x = torch.from_numpy(phantom(PhantomParams(shape=shape, seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
     n = x.numel()
     f = FCM(x, 4, timing=True)
-    f.autotune(reps=2)
+    f.autotune(cache=tune_cache, reps=2)
     timed_solves(f, 1)
     el, passes, kms, r = timed_solves(f, 3)
     tun = f.tuning
@@ -195,7 +204,7 @@ def large_volume(dev):
             "roofline_frac": ach / PEAK_LANE_OPS, "achieved_T_lane_op_s": ach / 1e12}
 
 
-def batched(dev):
+def batched(dev, tune_cache):
     import numpy as np
     import torch
 
@@ -207,6 +216,7 @@ def batched(dev):
     flat = torch.from_numpy(np.concatenate(xs)).to(dev)
     n = flat.numel()
     with FCMBatch(flat, [a.size for a in xs], [dict(n_clusters=c, m=2.0, eps=1e-5) for c in Cs]) as b:
+        cpt, bgrid, _ = b.autotune(cache=tune_cache, reps=1)
         b.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -237,7 +247,8 @@ def batched(dev):
                         "U{96..160}, C_i in 3..8, m=2, eps=1e-5",
             "voxels": n, "max_iterations": max(r.iters for r in res),
             "ms_per_batch_solve": el_b * 1e3, "voxel_iterations_per_s": vox_passes / el_b,
-            "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b}
+            "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b,
+            "tiling": {"chunks_per_thread": cpt, "grid": bgrid}}
 
 
 # ---- learned warm start (training set, held-out slices and volumes) ----------
@@ -378,7 +389,7 @@ def main():
     f.set_tuning(launch=0 if args.launch == "cooperative" else 1)
     tuned_ms = None
     if not args.no_autotune:
-        _, tuned_ms = f.autotune(reps=3)
+        _, tuned_ms = f.autotune(cache=args.tune_cache, reps=3)
     timed_solves(f, args.warmup, labels)
     tuning = f.tuning
     print(f"# warmup done, tuning {tuning}", file=sys.stderr, flush=True)
@@ -422,16 +433,16 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": recorded_traffic(shape, C, m),
+            "traffic": recorded_traffic(shape, C, m, tuning),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launch_avg_us": launch_s * 1e6,
             "alg_lane_ops_per_voxel_pass": alg_lane_ops(C, m, True),
         },
     }
     if not args.quick:
-        lv = large_volume(dev)
+        lv = large_volume(dev, args.tune_cache)
         print(f"# large volume: {lv['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
-        bt = batched(dev)
+        bt = batched(dev, args.tune_cache)
         print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
         ln = learned(dev, sets, x, C, m, eps, args.steps)
         out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln}
