@@ -204,6 +204,32 @@ def large_volume(dev, tune_cache):
             "roofline_frac": ach / PEAK_LANE_OPS, "achieved_T_lane_op_s": ach / 1e12}
 
 
+def histogram_domain(dev, x_head, shape_head):
+    """Exact histogram-domain solve (FCM_DRIVER_HISTOGRAM) on the headline
+    volume and the 512x512x256 volume: one pass over the data, then the
+    iteration over grey levels; time to converge with labels, against the
+    per-voxel persistent solve on the same handle configuration."""
+    import torch
+
+    from paper_1601_00072_amd import FCM
+    from phantom import PhantomParams, phantom
+    out = {}
+    big = torch.from_numpy(phantom(PhantomParams(shape=(256, 512, 512), seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
+    for name, x in (("1M volume " + "x".join(map(str, shape_head[::-1])), x_head), ("512x512x256 volume", big)):
+        labels = torch.empty_like(x)
+        res = {}
+        for drv in (3, 2):
+            with FCM(x, 4) as f:
+                f.set_tuning(driver=drv)
+                timed_solves(f, 2, labels)
+                el, passes, _, r = timed_solves(f, 10, labels)
+            res[drv] = (el / 10 * 1e3, r.iters)
+        out[name] = {"ms_to_converge_histogram": res[3][0], "iterations_histogram": res[3][1],
+                     "ms_to_converge_per_voxel": res[2][0], "iterations_per_voxel": res[2][1],
+                     "speedup": res[2][0] / res[3][0]}
+    return out
+
+
 def batched(dev, tune_cache):
     import numpy as np
     import torch
@@ -445,7 +471,9 @@ def main():
         bt = batched(dev, args.tune_cache)
         print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
         ln = learned(dev, sets, x, C, m, eps, args.steps)
-        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln}
+        hd = histogram_domain(dev, x, shape)
+        print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
+        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -68,6 +68,12 @@ extern "C" {
 #define FCM_DRIVER_PERSISTENT 2 /* one persistent launch runs the data-range pass
                                    and every pass of a solve (default where
                                    supported) */
+#define FCM_DRIVER_HISTOGRAM  3 /* histogram domain: one pass counts the grey levels,
+                                   then Algorithm 1 runs over the (at most 256)
+                                   levels present in FP64 in one block; every voxel
+                                   sum regroups exactly by level, so the result is the
+                                   same iteration (up to rounding order), and the data
+                                   are read once per solve */
 
 /* how the blocks of a persistent launch combine their partial sums each pass */
 #define FCM_EXCHANGE_AUTO      0  /* all-gather on small grids, else leader */

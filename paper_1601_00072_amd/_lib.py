@@ -32,6 +32,7 @@ FCM_F_TIMING = 1 << 1
 FCM_DRIVER_LOOP = 0
 FCM_DRIVER_GRAPH = 1
 FCM_DRIVER_PERSISTENT = 2
+FCM_DRIVER_HISTOGRAM = 3
 FCM_EXCHANGE_AUTO = 0
 FCM_EXCHANGE_LEADER = 1
 FCM_EXCHANGE_ALLGATHER = 2

@@ -177,6 +177,23 @@ hipError_t batch_max_grid(int ncu, int* max_grid);
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s);
 
+// Histogram-domain solve (one block; fcm_levels.hip).
+struct LevelArgs {
+    const uint32_t* counts;  // [256] grey-level counts of the input
+    DevState* st;
+    double* hist_v;
+    double* hist_d;
+    double* hist_J;
+    double eps, m;
+    int32_t max_iter;
+    int32_t do_init;         // compute the data range and v^0 first
+    int32_t given;           // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device)
+    int32_t max_passes;      // passes this launch may run
+    double v0[kMaxC];
+    const double* dv0;
+};
+hipError_t launch_levels(const LevelArgs& a, int C, hipStream_t s);
+
 using PassFn = void (*)(PassArgs);
 
 // Launchers (fcm_common.hip, fcm_dispatch.hip).  Return hipSuccess or the launch error.

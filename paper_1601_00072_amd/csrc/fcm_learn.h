@@ -20,6 +20,11 @@ int mlp_warm(fcm_mlp* net, const float* d_hist, int count, float* d_y, double* d
 // persistent solve's in-kernel inference); *rc receives an FCM_* status.
 const uint16_t* mlp_bf16_weights(fcm_mlp* net, hipStream_t s, int* rc);
 
+// Histograms of `count` instances: counts is a workspace of
+// count * histogram_copies(count) * 256 words; on completion copy 0 of each
+// instance's counts holds its integer totals and hist[count][256] the
+// normalised histogram.
+int histogram_copies(int count);
 hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
                             float* hist, hipStream_t s);
 hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* Cm, int M, int N, int K,

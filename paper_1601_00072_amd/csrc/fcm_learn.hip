@@ -17,16 +17,21 @@
 
 namespace fcm {
 
+constexpr int kWaveTables = kBlock / 64;
+
 // ---------------------------------------------------------------------------
 // histogram of each instance (integer counts, then normalised to sum 1)
 // ---------------------------------------------------------------------------
 
+// counts layout: [count][copies][256]; block x of instance y adds into copy
+// x % copies (spreads the atomics of one busy level over `copies` addresses)
 __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint8_t* x, const int64_t* offsets,
-                                                            uint32_t* counts) {
-    __shared__ uint32_t bins[256];
+                                                            uint32_t* counts, int copies) {
+    __shared__ uint32_t bins[kWaveTables][256];
     const int inst = blockIdx.y;
     const int tid = threadIdx.x;
-    bins[tid] = 0u;
+    uint32_t* mine = bins[tid >> 6];  // one table per wave: fewer same-address conflicts
+    for (int w = 0; w < kWaveTables; ++w) bins[w][tid] = 0u;
     __syncthreads();
     const int64_t b0 = offsets[inst], n = offsets[inst + 1] - b0;
     const uint8_t* xi = x + b0;
@@ -40,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint8_t* x, co
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&bins[(words[q] >> (8 * b)) & 0xFFu], 1u);
+            for (int b = 0; b < 4; ++b) atomicAdd(&mine[(words[q] >> (8 * b)) & 0xFFu], 1u);
         }
     }
     if (blockIdx.x == 0) {
@@ -48,36 +53,46 @@ __global__ __launch_bounds__(kBlock) void hist_count_kernel(const uint8_t* x, co
         const int64_t nr = head + (n - tail0);
         for (int64_t r = tid; r < nr; r += kBlock) {
             const int64_t i = r < head ? r : tail0 + (r - head);
-            atomicAdd(&bins[xi[i]], 1u);
+            atomicAdd(&mine[xi[i]], 1u);
         }
     }
     __syncthreads();
-    if (bins[tid]) atomicAdd(counts + (int64_t)inst * 256 + tid, bins[tid]);
+    uint32_t c = 0u;
+    for (int w = 0; w < kWaveTables; ++w) c += bins[w][tid];
+    if (c) atomicAdd(counts + ((int64_t)inst * copies + blockIdx.x % copies) * 256 + tid, c);
 }
 
-__global__ __launch_bounds__(kBlock) void hist_norm_kernel(const uint32_t* counts, const int64_t* offsets,
-                                                           float* hist) {
+// totals of the copies -> copy 0 (integer counts) and count / n (FP64, stored FP32)
+__global__ __launch_bounds__(kBlock) void hist_norm_kernel(uint32_t* counts, const int64_t* offsets, float* hist,
+                                                           int copies) {
     const int inst = blockIdx.x;
-    const int64_t o = (int64_t)inst * 256 + threadIdx.x;
-    hist[o] = hist_norm(counts[o], offsets[inst + 1] - offsets[inst]);
+    uint32_t* ci = counts + (int64_t)inst * copies * 256;
+    uint32_t total = 0u;
+    for (int c = 0; c < copies; ++c) total += ci[c * 256 + threadIdx.x];
+    ci[threadIdx.x] = total;
+    hist[(int64_t)inst * 256 + threadIdx.x] = hist_norm(total, offsets[inst + 1] - offsets[inst]);
 }
+
+int histogram_copies(int count) { return count == 1 ? kHistCopies : 1; }
 
 hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
                             float* hist, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * 256 * (size_t)count, s);
+    const int copies = histogram_copies(count);
+    hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * 256 * (size_t)count * copies, s);
     if (e != hipSuccess) return e;
     const int64_t chunks = (max_n + 15) / 16;
+    const int64_t cap = count == 1 ? 1024 : 64;  // a single instance may use the whole device
     int64_t gx64 = (chunks + kBlock * 16 - 1) / (kBlock * 16);
-    gx64 = gx64 < 1 ? 1 : (gx64 > 64 ? 64 : gx64);
+    gx64 = gx64 < 1 ? 1 : (gx64 > cap ? cap : gx64);
     const int gx = (int)gx64;
     constexpr int kMaxY = 65535;  // grid y limit: instances per launch
     for (int c0 = 0; c0 < count; c0 += kMaxY) {
         const int cnt = count - c0 < kMaxY ? count - c0 : kMaxY;
         hipLaunchKernelGGL(hist_count_kernel, dim3(gx, cnt), dim3(kBlock), 0, s, x, d_offsets + c0,
-                           counts + (int64_t)c0 * 256);
+                           counts + (int64_t)c0 * copies * 256, copies);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(hist_norm_kernel, dim3(count), dim3(256), 0, s, counts, d_offsets, hist);
+    hipLaunchKernelGGL(hist_norm_kernel, dim3(count), dim3(256), 0, s, counts, d_offsets, hist, copies);
     return hipGetLastError();
 }
 

@@ -357,7 +357,7 @@ int fcm_histogram(const uint8_t* d_x, const int64_t* offsets, int32_t count, flo
     int64_t* d_off = nullptr;
     uint32_t* d_counts = nullptr;
     if (hipMalloc(&d_off, sizeof(int64_t) * ((size_t)count + 1)) != hipSuccess) return FCM_ENOMEM;
-    if (hipMalloc(&d_counts, sizeof(uint32_t) * 256 * (size_t)count) != hipSuccess) {
+    if (hipMalloc(&d_counts, sizeof(uint32_t) * 256 * (size_t)count * histogram_copies(count)) != hipSuccess) {
         (void)hipFree(d_off);
         return FCM_ENOMEM;
     }

@@ -70,7 +70,8 @@ int validate_tuning(const fcm_tuning* t) {
     if (t->block != kBlock) return FCM_EINVAL;
     if (t->grid < 0 || t->grid > kMaxGrid) return FCM_EINVAL;
     if (t->unroll != 1 && t->unroll != 2) return FCM_EINVAL;
-    if (t->driver != FCM_DRIVER_LOOP && t->driver != FCM_DRIVER_GRAPH && t->driver != FCM_DRIVER_PERSISTENT)
+    if (t->driver != FCM_DRIVER_LOOP && t->driver != FCM_DRIVER_GRAPH && t->driver != FCM_DRIVER_PERSISTENT &&
+        t->driver != FCM_DRIVER_HISTOGRAM)
         return FCM_EINVAL;
     if (t->graph_k < 1 || t->graph_k > kMaxGraphK) return FCM_EINVAL;
     if (t->exchange < FCM_EXCHANGE_AUTO || t->exchange > FCM_EXCHANGE_ALLGATHER) return FCM_EINVAL;
@@ -118,7 +119,7 @@ struct fcm_handle {
 
     // warm start workspace (first fcm_solve_warm)
     int64_t* d_woff = nullptr;     // {0, n}
-    uint32_t* d_wcounts = nullptr; // [256]
+    uint32_t* d_wcounts = nullptr; // [kHistCopies][256] histogram workspace (copy 0: totals)
     float* d_whist = nullptr;      // [256]
     float* d_wy = nullptr;         // [kMaxC] network output
     double* d_wv0 = nullptr;       // [kMaxC] learned start
@@ -278,9 +279,45 @@ int flush_init(fcm_handle* h) {
     return FCM_OK;
 }
 
+int ensure_level_ws(fcm_handle* h);
+
 // Run up to `batch` passes and read the state back once.
 int run_batch(fcm_handle* h, int batch) {
     const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
+    if (h->tun.driver == FCM_DRIVER_HISTOGRAM) {
+        int rc = ensure_level_ws(h);
+        if (rc != FCM_OK) return rc;
+        LevelArgs la{};
+        la.counts = h->d_wcounts;  // copy 0: the totals
+        la.st = h->d_state;
+        la.hist_v = h->hist_v();
+        la.hist_d = h->hist_d();
+        la.hist_J = h->hist_J();
+        la.eps = h->p.eps;
+        la.m = h->p.m;
+        la.max_iter = h->p.max_iter;
+        la.do_init = h->pending_init ? 1 : 0;
+        la.given = start_mode(h->p.init);
+        for (int k = 0; k < kMaxC; ++k) la.v0[k] = h->given[k];
+        la.dv0 = h->dv0;
+        la.max_passes = batch;
+        if (timing) {
+            if ((rc = ensure_events(h, 2)) != FCM_OK) return rc;
+            FCM_HIP(hipEventRecord(h->ev[0], h->stream));
+        }
+        if (h->pending_init)
+            FCM_HIP(launch_histogram(h->d_x, h->d_woff, 1, h->n, h->d_wcounts, h->d_whist, h->stream));
+        FCM_HIP(launch_levels(la, h->p.n_clusters, h->stream));
+        h->pending_init = false;
+        if (timing) FCM_HIP(hipEventRecord(h->ev[1], h->stream));
+        if ((rc = read_state(h)) != FCM_OK) return rc;
+        if (timing) {
+            float ms = 0.f;
+            FCM_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+            h->kernel_ms += ms;
+        }
+        return FCM_OK;
+    }
     if (h->tun.driver == FCM_DRIVER_PERSISTENT) {
         PassArgs a = pass_args(h);
         a.max_passes = batch;
@@ -336,6 +373,28 @@ int run_batch(fcm_handle* h, int batch) {
             h->kernel_ms += ms;
         }
     }
+    return FCM_OK;
+}
+
+// Grey-level workspace of a handle (histogram, network output, learned
+// start), allocated on first use by the warm start or the histogram driver.
+int ensure_level_ws(fcm_handle* h) {
+    if (h->d_woff) return FCM_OK;
+    if (!h->d_wcounts && hipMalloc(&h->d_wcounts, sizeof(uint32_t) * 256 * histogram_copies(1)) != hipSuccess)
+        return FCM_ENOMEM;
+    if (!h->d_whist && hipMalloc(&h->d_whist, sizeof(float) * 256) != hipSuccess) return FCM_ENOMEM;
+    if (!h->d_wy && hipMalloc(&h->d_wy, sizeof(float) * kMaxC) != hipSuccess) return FCM_ENOMEM;
+    if (!h->d_wv0 && hipMalloc(&h->d_wv0, sizeof(double) * kMaxC) != hipSuccess) return FCM_ENOMEM;
+    int64_t* off = nullptr;
+    if (hipMalloc(&off, sizeof(int64_t) * 2) != hipSuccess) return FCM_ENOMEM;
+    const int64_t range[2] = {0, h->n};
+    hipError_t e = hipMemcpyAsync(off, range, sizeof(range), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(off);
+        return dev_err(e, "hipMemcpyAsync");
+    }
+    h->d_woff = off;
     return FCM_OK;
 }
 
@@ -505,7 +564,9 @@ int fcm_iterate(fcm_handle* h, int32_t k, fcm_result* out) {
     if (rc != FCM_OK) return rc;
     int remaining = k;
     while (remaining > 0 && (h->pending_init || !h->h_state->done)) {
-        const int batch = h->tun.driver == FCM_DRIVER_PERSISTENT ? remaining : std::min(remaining, h->tun.graph_k);
+        const int batch = (h->tun.driver == FCM_DRIVER_PERSISTENT || h->tun.driver == FCM_DRIVER_HISTOGRAM)
+                              ? remaining
+                              : std::min(remaining, h->tun.graph_k);
         rc = run_batch(h, batch);
         if (rc != FCM_OK) return rc;
         remaining -= batch;
@@ -527,7 +588,9 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
     const int64_t total = (int64_t)h->p.max_iter + 1;
     int64_t budget = total + h->tun.graph_k;
     while ((h->pending_init || !h->h_state->done) && budget > 0) {
-        const int batch = h->tun.driver == FCM_DRIVER_PERSISTENT ? (int)total : h->tun.graph_k;
+        const int batch = (h->tun.driver == FCM_DRIVER_PERSISTENT || h->tun.driver == FCM_DRIVER_HISTOGRAM)
+                              ? (int)total
+                              : h->tun.graph_k;
         rc = run_batch(h, batch);
         if (rc != FCM_OK) return rc;
         budget -= batch;
@@ -539,20 +602,9 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
 int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain, int32_t* used) {
     if (!h || !net || !out) return FCM_EINVAL;
     if (mlp_clusters(net) != h->p.n_clusters) return FCM_EINVAL;
-    if (!h->d_woff) {
-        if (hipMalloc(&h->d_wcounts, sizeof(uint32_t) * 256) != hipSuccess) return FCM_ENOMEM;
-        if (hipMalloc(&h->d_whist, sizeof(float) * 256) != hipSuccess) return FCM_ENOMEM;
-        if (hipMalloc(&h->d_wy, sizeof(float) * kMaxC) != hipSuccess) return FCM_ENOMEM;
-        if (hipMalloc(&h->d_wv0, sizeof(double) * kMaxC) != hipSuccess) return FCM_ENOMEM;
-        int64_t* off = nullptr;
-        if (hipMalloc(&off, sizeof(int64_t) * 2) != hipSuccess) return FCM_ENOMEM;
-        const int64_t range[2] = {0, h->n};
-        FCM_HIP(hipMemcpyAsync(off, range, sizeof(range), hipMemcpyHostToDevice, h->stream));
-        FCM_HIP(hipStreamSynchronize(h->stream));
-        h->d_woff = off;
-    }
+    int rc = ensure_level_ws(h);
+    if (rc != FCM_OK) return rc;
     fcm_result rp{}, rw{};
-    int rc;
     if (check) {  // the plain solve from the handle's own start
         if ((rc = enqueue_start(h)) != FCM_OK) return rc;
         if ((rc = fcm_solve(h, &rp)) < 0) return rc;
@@ -869,7 +921,8 @@ int fcm_batch_set_start(fcm_batch* b, fcm_mlp* net, const uint8_t* use_learned) 
     if (net) {
         const size_t cnt = (size_t)b->count;
         if (!b->d_off) {
-            if (hipMalloc(&b->d_counts, sizeof(uint32_t) * 256 * cnt) != hipSuccess) return FCM_ENOMEM;
+            if (hipMalloc(&b->d_counts, sizeof(uint32_t) * 256 * cnt * histogram_copies(b->count)) != hipSuccess)
+                return FCM_ENOMEM;
             if (hipMalloc(&b->d_whist, sizeof(float) * 256 * cnt) != hipSuccess) return FCM_ENOMEM;
             if (hipMalloc(&b->d_wy, sizeof(float) * kMaxC * cnt) != hipSuccess) return FCM_ENOMEM;
             if (hipMalloc(&b->d_wv0, sizeof(double) * kMaxC * cnt) != hipSuccess) return FCM_ENOMEM;
