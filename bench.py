@@ -230,6 +230,40 @@ def histogram_domain(dev, x_head, shape_head):
     return out
 
 
+def quality(dev, shape, seed):
+    """Dice coefficient per tissue (Eq.5) of the GPU segmentation of the
+    headline volume and of the 512x512x256 volume against the phantoms'
+    tissue labels, and the time of the confusion-count + Dice kernels."""
+    import torch
+
+    from paper_1601_00072_amd import FCM, confusion, dice, rank_classes
+    from phantom import PhantomParams, phantom
+    out = {}
+    cases = (("1M volume " + "x".join(map(str, shape[::-1])), PhantomParams(shape=shape, seed=seed)),
+             ("512x512x256 volume", PhantomParams(shape=(256, 512, 512), seed=3, sigma=9.0, bias=0.2)))
+    for name, p in cases:
+        img, lab = phantom(p, with_labels=True)
+        x = torch.from_numpy(img.ravel()).to(dev)
+        truth = torch.from_numpy(lab.ravel()).to(dev)
+        with FCM(x, 4) as f:
+            r = f.solve()
+            labels = f.labels()
+        cls = rank_classes(r.centroids, 4)
+        d = dice(confusion(labels, truth, 4, 4), 4, 4, cls)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            d = dice(confusion(labels, truth, 4, 4), 4, 4, cls)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        out[name] = {"dsc": dict(zip(("background", "CSF", "GM", "WM"), d.cpu().tolist())),
+                     "us_confusion_and_dice": us, "confusion_GB_per_s": 2 * x.numel() / (us * 1e-6) / 1e9}
+    return out
+
+
 def batched(dev, tune_cache):
     import numpy as np
     import torch
@@ -473,7 +507,10 @@ def main():
         ln = learned(dev, sets, x, C, m, eps, args.steps)
         hd = histogram_domain(dev, x, shape)
         print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
-        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd}
+        q = quality(dev, shape, args.seed)
+        print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
+        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
+                        "segmentation_quality": q}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -332,6 +332,27 @@ int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, 
  * batch's stream (allocating their buffers on the first call). */
 int fcm_batch_set_start(fcm_batch* b, fcm_mlp* net, const uint8_t* use_learned);
 
+/* ---- segmentation quality (Sec. 5.2.2, Eq.5) ----------------------------- */
+
+/* Confusion counts of two label images over n voxels (device, any alignment):
+ * d_counts[j * n_truth + k] = number of voxels with d_pred == j and
+ * d_truth == k, and d_counts[n_pred * n_truth] = number of voxels whose pred
+ * or truth value lies outside [0, n_pred) or [0, n_truth).  d_counts is a
+ * device array of n_pred * n_truth + 1 counters, cleared by the call.
+ * 1 <= n_pred, n_truth <= 16; n >= 0 (n = 0 leaves all counts zero).
+ * Enqueued on the stream, not waited for. */
+int fcm_confusion(const uint8_t* d_pred, const uint8_t* d_truth, int64_t n, int32_t n_pred, int32_t n_truth,
+                  uint64_t* d_counts, void* stream);
+
+/* Dice similarity coefficient per ground-truth class (Eq.5) from confusion
+ * counts made by fcm_confusion: cluster j is counted as class class_of[j]
+ * (host, n_pred values in [-1, n_truth), -1 = no class; NULL maps cluster j
+ * to class j where j < n_truth).  d_dsc (device, n_truth doubles) receives
+ * 2 |PR_k and GT_k| / (|PR_k| + |GT_k|), rounded once from the exact counts,
+ * or NaN where both sets are empty.  Enqueued on the stream, not waited for. */
+int fcm_dice(const uint64_t* d_counts, int32_t n_pred, int32_t n_truth, const int32_t* class_of, double* d_dsc,
+             void* stream);
+
 /* Static description of a status code, and the last HIP error text of this thread. */
 const char* fcm_strerror(int status);
 const char* fcm_last_error(void);

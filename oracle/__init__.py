@@ -12,4 +12,5 @@ Modules
   exact      the same iteration in exact rational (m = 2, 3) or 60-digit
              decimal arithmetic, for tiny inputs
   mlp_ref    FP64 forward/backward of the histogram -> centroid network
+  dice       confusion counts and the Dice coefficient of Eq.5 per tissue
 """

@@ -47,6 +47,7 @@ EXPORTS = (
     "fcm_batch_destroy", "fcm_mlp_param_count", "fcm_mlp_create", "fcm_mlp_get_params", "fcm_mlp_set_params",
     "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
+    "fcm_confusion", "fcm_dice",
 )
 
 
@@ -174,6 +175,10 @@ def load() -> ctypes.CDLL:
     lib.fcm_mlp_destroy.restype = None
     lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
     lib.fcm_histogram.restype = ctypes.c_int
+    lib.fcm_confusion.argtypes = [vp, vp, i64, i32, i32, vp, vp]
+    lib.fcm_confusion.restype = ctypes.c_int
+    lib.fcm_dice.argtypes = [vp, i32, i32, ctypes.POINTER(i32), vp, vp]
+    lib.fcm_dice.restype = ctypes.c_int
     lib.fcm_warm_centroids.argtypes = [vp, vp, i32, vp, vp]
     lib.fcm_warm_centroids.restype = ctypes.c_int
     lib.fcm_solve_warm.argtypes = [vp, vp, i32, ctypes.POINTER(FcmResult), ctypes.POINTER(FcmResult),

@@ -354,6 +354,56 @@ def histogram(x, sizes, stream=None):
     return out
 
 
+def confusion(pred, truth, n_pred: int, n_truth: int, stream=None):
+    """Confusion counts of two uint8 label tensors on the device (Sec. 5.2.2):
+    an int64 device tensor [n_pred * n_truth + 1]; entry j * n_truth + k counts
+    voxels with pred j and truth k, the last one voxels outside the ranges."""
+    import torch
+    lib = L.load()
+    if pred.dtype != torch.uint8 or truth.dtype != torch.uint8 or pred.numel() != truth.numel():
+        raise ValueError("pred and truth must be uint8 tensors of equal size")
+    if not (pred.is_contiguous() and truth.is_contiguous()):
+        raise ValueError("pred and truth must be contiguous")
+    out = torch.empty(int(n_pred) * int(n_truth) + 1, dtype=torch.int64, device=pred.device)
+    st = stream if stream is not None else torch.cuda.current_stream(pred.device)
+    rc = lib.fcm_confusion(ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(truth.data_ptr()), pred.numel(),
+                           int(n_pred), int(n_truth), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+    if rc != L.FCM_OK:
+        raise FcmError(rc, "fcm_confusion")
+    return out
+
+
+def dice(counts, n_pred: int, n_truth: int, class_of=None, stream=None):
+    """Dice coefficient per ground-truth class (Eq.5) from confusion counts;
+    cluster j counts as class class_of[j] (-1: none; None: class j).  Returns
+    a float64 device tensor [n_truth] (NaN where both sets are empty)."""
+    import torch
+    lib = L.load()
+    out = torch.empty(int(n_truth), dtype=torch.float64, device=counts.device)
+    st = stream if stream is not None else torch.cuda.current_stream(counts.device)
+    cls = None
+    if class_of is not None:
+        arr = (ctypes.c_int32 * int(n_pred))(*[int(v) for v in class_of])
+        cls = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    rc = lib.fcm_dice(ctypes.c_void_p(counts.data_ptr()), int(n_pred), int(n_truth), cls,
+                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+    if rc != L.FCM_OK:
+        raise FcmError(rc, "fcm_dice")
+    return out
+
+
+def rank_classes(centroids, n_truth: int):
+    """Cluster -> class map by intensity order: the cluster with the k-th
+    smallest centroid is class k (ties by index; ranks >= n_truth map to -1).
+    For ground truths whose classes are numbered by increasing mean grey
+    level, like the phantom's background, CSF, GM, WM."""
+    order = sorted(range(len(centroids)), key=lambda j: (float(centroids[j]), j))
+    cls = [-1] * len(centroids)
+    for r, j in enumerate(order):
+        cls[j] = r if r < n_truth else -1
+    return cls
+
+
 class MLP:
     """Histogram -> centroid network (256 -> 128 -> 64 -> C), trained and run
     by the library's kernels.  Inputs are normalised histograms (float32

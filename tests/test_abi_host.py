@@ -158,3 +158,20 @@ def test_autotune_validation(lib):
     ms = ctypes.c_double()
     assert lib.fcm_autotune(None, None, 3, ctypes.byref(t), ctypes.byref(ms)) == L.FCM_EINVAL
     assert lib.fcm_batch_autotune(None, None, 2, None, None, None) == L.FCM_EINVAL
+
+
+def test_quality_validation(lib):
+    """Argument checks of the Eq.5 entry points return before any device call."""
+    i32 = ctypes.c_int32
+    assert lib.fcm_confusion(FAKE, FAKE, 10, 0, 4, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_confusion(FAKE, FAKE, 10, 4, 17, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_confusion(FAKE, FAKE, -1, 4, 4, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_confusion(None, FAKE, 10, 4, 4, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_confusion(FAKE, FAKE, 10, 4, 4, None, None) == L.FCM_EINVAL
+    assert lib.fcm_dice(None, 4, 4, None, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_dice(FAKE, 4, 4, None, None, None) == L.FCM_EINVAL
+    assert lib.fcm_dice(FAKE, 17, 4, None, FAKE, None) == L.FCM_EINVAL
+    bad = (i32 * 4)(0, 1, 4, 2)
+    assert lib.fcm_dice(FAKE, 4, 4, bad, FAKE, None) == L.FCM_EINVAL
+    bad = (i32 * 4)(0, -2, 1, 2)
+    assert lib.fcm_dice(FAKE, 4, 4, bad, FAKE, None) == L.FCM_EINVAL
