@@ -137,17 +137,36 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fcm_persist_kernel_volume_1M_c
 TUNE_CACHE = os.path.join(ROOT, "paper_1601_00072_amd", "tuning_mi355x.txt")
 
 
-def sources_digest() -> str:
-    """SHA-256 prefix over the library's device sources (.hip, .h)."""
+def kernel_sources(C: int) -> list:
+    """The files the persistent kernel for C clusters is compiled from: its
+    translation unit and every quoted include it reaches, recursively."""
+    import re
+    dirs = [os.path.join(ROOT, "paper_1601_00072_amd", "csrc"), os.path.join(ROOT, "include")]
+    todo, seen = [os.path.join(dirs[0], f"fcm_pass_c{C}.hip")], []
+    while todo:
+        path = todo.pop()
+        if path in seen:
+            continue
+        seen.append(path)
+        with open(path) as fh:
+            for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), flags=re.M):
+                for d in dirs:
+                    cand = os.path.join(d, inc)
+                    if os.path.exists(cand):
+                        todo.append(cand)
+                        break
+    return sorted(seen)
+
+
+def sources_digest(C: int = 4) -> str:
+    """SHA-256 prefix over the sources of the persistent kernel (kernel_sources)."""
     import hashlib
     h = hashlib.sha256()
-    src = os.path.join(ROOT, "paper_1601_00072_amd", "csrc")
-    for name in sorted(os.listdir(src)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(b"\0")
-            with open(os.path.join(src, name), "rb") as fh:
-                h.update(fh.read())
+    for path in kernel_sources(C):
+        h.update(os.path.relpath(path, ROOT).encode())
+        h.update(b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -165,7 +184,7 @@ def recorded_traffic(shape, C, m, tuning):
                 f = line.split()
                 if f[:1] == ["traffic_bytes_per_launch:"]:
                     kv = dict(zip(f[0::2], f[1::2]))
-                    same = (kv.get("sources_digest:") == sources_digest()
+                    same = (kv.get("sources_digest:") == sources_digest(C)
                             and kv.get("tuning:") == tuning_tag(tuning)
                             and kv.get("workload:") == ",".join(map(str, shape))
                             and f"C={C}" in f and f"m={float(m)}" in f)
