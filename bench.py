@@ -249,6 +249,31 @@ def histogram_domain(dev, x_head, shape_head):
     return out
 
 
+def paper_protocol(dev, x, shape):
+    """The paper's own protocol on the headline volume: random memberships U^0
+    (five seeds), centroids first, eps = 0.005; iterations, time to converge
+    (labels included) and the final centroids, beside the evenly spaced
+    start at the same eps."""
+    import torch
+
+    from paper_1601_00072_amd import FCM
+    labels = torch.empty_like(x)
+    runs = []
+    for seed in range(1, 6):
+        with FCM(x, 4, eps=0.005, init=("random_u", seed)) as f:
+            timed_solves(f, 2, labels)
+            el, _, _, r = timed_solves(f, 10, labels)
+        runs.append({"seed": seed, "iterations": r.iters, "ms_to_converge": el / 10 * 1e3,
+                     "centroids": [round(float(v), 4) for v in r.centroids]})
+    with FCM(x, 4, eps=0.005) as f:
+        timed_solves(f, 2, labels)
+        el, _, _, r = timed_solves(f, 10, labels)
+    return {"workload": "1M volume " + "x".join(map(str, shape[::-1])) + ", C=4, m=2, eps=0.005",
+            "random_u": runs,
+            "linspace": {"iterations": r.iters, "ms_to_converge": el / 10 * 1e3,
+                         "centroids": [round(float(v), 4) for v in r.centroids]}}
+
+
 def quality(dev, shape, seed):
     """Dice coefficient per tissue (Eq.5) of the GPU segmentation of the
     headline volume and of the 512x512x256 volume against the phantoms'
@@ -528,8 +553,10 @@ def main():
         print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
         q = quality(dev, shape, args.seed)
         print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
+        pp = paper_protocol(dev, x, shape)
+        print(f"# paper protocol: {pp}", file=sys.stderr, flush=True)
         out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
-                        "segmentation_quality": q}
+                        "segmentation_quality": q, "paper_protocol": pp}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -56,6 +56,14 @@ extern "C" {
                                    array init_centroids (C doubles, borrowed), rounded
                                    to FP32; any non-finite value selects LINSPACE.
                                    Used by the learned warm start. */
+#define FCM_INIT_RANDOM_U 3     /* the paper's start (Sec. 2.1, Algorithm 1): random
+                                   memberships U^0, u_ij = r_ij / sum_k r_ik with r_ij
+                                   = (top 24 bits of draw i C + j of the SplitMix64
+                                   stream `seed`, plus 1) / 2^24, then the centroids
+                                   first: pass 0 computes v^1 from U^0, pass 1 tests
+                                   U^1 against U^0.  v^0, J^0 and delta^0 are NaN.
+                                   Not for batches or the histogram driver (U^0 is not
+                                   a function of the grey level). */
 
 /* flags */
 #define FCM_F_KAHAN_ONLY  (1u << 0)  /* cross-block reduction in compensated FP32
@@ -98,6 +106,7 @@ typedef struct fcm_params {
     const double* init_centroids; /* FCM_INIT_GIVEN: host, C finite values (copied);
                                      FCM_INIT_DEVICE: device, C values (borrowed) */
     uint32_t flags;               /* FCM_F_* */
+    uint64_t seed;                /* FCM_INIT_RANDOM_U: the generator stream (else ignored) */
 } fcm_params;
 
 typedef struct fcm_tuning {

@@ -8,9 +8,11 @@ Readings of points the paper leaves open (listed with the rest in the design
 notes):
   * Eq.3 is printed with v_i and Eq.1 is labelled J_i; read as v_j and J_m.
   * m must exceed 1 (the exponent 2/(m-1) is undefined at m = 1).
-  * Initialisation is centroid-first: v^0 is given (default: evenly spaced
+  * Initialisation, default: centroid-first, v^0 is given (evenly spaced
     over [min, max] including both ends, computed in FP64 and rounded to FP32),
-    then U^0 = memb(v^0).  The paper initialises U randomly instead.
+    then U^0 = memb(v^0).  The paper's own protocol (``solve_random_u``):
+    U^0 random (positive weights per voxel normalised to sum 1, Eq.2), then
+    the centroids first.
   * Stopping test: max_{i,j} |u_ij^t - u_ij^(t-1)| < eps, strict.
   * Zero distance (Eq.4 divides by zero): the membership is split equally
     over the clusters at distance 0 (membership 1 when only one is).
@@ -114,6 +116,39 @@ def solve(x: np.ndarray, C: int, m: float = 2.0, eps: float = 1e-5, max_iter: in
     v = np.asarray(v0, dtype=np.float64).copy()
     U = memberships(x, v, m)
     vs, ds, Js = [v.copy()], [float("nan")], [objective(x, U, v, m)]
+    status, T = NOT_CONVERGED, max_iter
+    for t in range(1, max_iter + 1):
+        v = centroids(x, U, m, v)
+        U_new = memberships(x, v, m)
+        delta = float(np.max(np.abs(U_new - U)))
+        U = U_new
+        vs.append(v.copy())
+        ds.append(delta)
+        Js.append(objective(x, U, v, m))
+        if delta < eps:
+            status, T = OK, t
+            break
+    return Trajectory(v=vs, delta=ds, J=Js, T=T, status=status)
+
+
+def random_memberships(r: np.ndarray) -> np.ndarray:
+    """U^0 from positive random weights r [n][C]: each row divided by its sum,
+    so that Eq.2 holds."""
+    r = np.asarray(r, dtype=np.float64)
+    return r / r.sum(axis=1, keepdims=True)
+
+
+def solve_random_u(x: np.ndarray, C: int, m: float, eps: float, max_iter: int, r: np.ndarray) -> Trajectory:
+    """Algorithm 1 as the paper runs it: U^0 random (from the weights r, see
+    random_memberships), then for t = 1..max_iter: v^t = cent(U^(t-1)) (Eq.3),
+    U^t = memb(v^t) (Eq.4), delta^t = max |U^t - U^(t-1)|; stop with T = t
+    when delta^t < eps.  No centroids exist before the first update, so v[0],
+    delta[0] and J[0] are NaN; the result is v^T as in ``solve``."""
+    x = np.asarray(x).ravel()
+    U = random_memberships(r)
+    assert U.shape == (x.size, C)
+    v = np.full(C, np.nan)
+    vs, ds, Js = [v.copy()], [float("nan")], [float("nan")]
     status, T = NOT_CONVERGED, max_iter
     for t in range(1, max_iter + 1):
         v = centroids(x, U, m, v)

@@ -25,6 +25,7 @@ FCM_MAX_CLUSTERS = 8
 FCM_INIT_LINSPACE = 0
 FCM_INIT_GIVEN = 1
 FCM_INIT_DEVICE = 2
+FCM_INIT_RANDOM_U = 3
 FCM_MLP_FP32 = 0
 FCM_MLP_BF16 = 1
 FCM_F_KAHAN_ONLY = 1 << 0
@@ -60,6 +61,7 @@ class FcmParams(ctypes.Structure):
         ("init", ctypes.c_int32),
         ("init_centroids", ctypes.POINTER(ctypes.c_double)),
         ("flags", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
     ]
 
 

@@ -52,8 +52,9 @@ def _stream_handle(stream, device):
 class FCM:
     """Fuzzy C-Means solver over a uint8 device tensor (any shape, contiguous).
 
-    ``init`` is None (evenly spaced over the data range) or a sequence of C
-    starting centroids.  The tensor is borrowed: keep it alive and unmodified
+    ``init`` is None (evenly spaced over the data range), a sequence of C
+    starting centroids, or ``("random_u", seed)`` for the paper's own start
+    (random memberships from the SplitMix64 stream ``seed``, centroids first).  The tensor is borrowed: keep it alive and unmodified
     while the solver exists."""
 
     def __init__(self, x, n_clusters: int, m: float = 2.0, eps: float = 1e-5, max_iter: int = 300,
@@ -70,8 +71,11 @@ class FCM:
         self._stream = stream if stream is not None else torch.cuda.current_stream(x.device)
         flags = (L.FCM_F_KAHAN_ONLY if kahan_only else 0) | (L.FCM_F_TIMING if timing else 0)
         self._init_buf = None
+        seed = 0
         if init is None:
             mode, ptr = L.FCM_INIT_LINSPACE, None
+        elif isinstance(init, tuple) and len(init) == 2 and init[0] == "random_u":
+            mode, ptr, seed = L.FCM_INIT_RANDOM_U, None, int(init[1]) & ((1 << 64) - 1)
         else:
             v = np.ascontiguousarray(np.asarray(init, dtype=np.float64))
             if v.shape != (self.C,):
@@ -79,7 +83,7 @@ class FCM:
             self._init_buf = (ctypes.c_double * self.C)(*v.tolist())
             mode, ptr = L.FCM_INIT_GIVEN, ctypes.cast(self._init_buf, ctypes.POINTER(ctypes.c_double))
         p = L.FcmParams(n_clusters=self.C, m=float(m), eps=float(eps), max_iter=int(max_iter), init=mode,
-                        init_centroids=ptr, flags=flags)
+                        init_centroids=ptr, flags=flags, seed=seed)
         self._h = ctypes.c_void_p()
         rc = self._lib.fcm_init(ctypes.byref(self._h), ctypes.c_void_p(x.data_ptr()), self.n, ctypes.byref(p),
                                 ctypes.c_void_p(self._stream.cuda_stream))

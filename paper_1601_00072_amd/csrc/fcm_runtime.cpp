@@ -21,6 +21,7 @@
 
 #include "fcm.h"
 #include "fcm_host.h"
+#include "fcm_random.h"
 #include "fcm_internal.h"
 #include "fcm_learn.h"
 
@@ -53,7 +54,9 @@ int validate_params(const fcm_params* p) {
     if (!std::isfinite(p->m) || !(p->m > 1.0)) return FCM_EINVAL;
     if (!std::isfinite(p->eps) || !(p->eps > 0.0)) return FCM_EINVAL;
     if (p->max_iter < 1 || p->max_iter > (1 << 24)) return FCM_EINVAL;
-    if (p->init != FCM_INIT_LINSPACE && p->init != FCM_INIT_GIVEN && p->init != FCM_INIT_DEVICE) return FCM_EINVAL;
+    if (p->init != FCM_INIT_LINSPACE && p->init != FCM_INIT_GIVEN && p->init != FCM_INIT_DEVICE &&
+        p->init != FCM_INIT_RANDOM_U)
+        return FCM_EINVAL;
     if (p->init == FCM_INIT_DEVICE && !p->init_centroids) return FCM_EINVAL;
     if (p->init == FCM_INIT_GIVEN) {
         if (!p->init_centroids) return FCM_EINVAL;
@@ -281,9 +284,46 @@ int flush_init(fcm_handle* h) {
 
 int ensure_level_ws(fcm_handle* h);
 
+// Random-membership start: the data-range pass (for lo, hi), then those of
+// passes 0 and 1 that are still due, from the budget `batch`, launched back
+// to back (each kernel checks the pass counter) with one read-back.
+int run_random_start(fcm_handle* h, int& batch) {
+    int rc = flush_init(h);
+    if (rc != FCM_OK) return rc;
+    const int first = h->h_state->passes;
+    if (first >= 2 || h->h_state->done || batch < 1) return FCM_OK;
+    const int last = std::min(2, first + batch);
+    const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
+    if (timing) {
+        if ((rc = ensure_events(h, 2)) != FCM_OK) return rc;
+        FCM_HIP(hipEventRecord(h->ev[0], h->stream));
+    }
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunk_blocks(h), std::min<int64_t>(4LL * h->ncu,
+                                                                                                     kMaxGrid)));
+    const PassArgs a = pass_args(h);
+    for (int phase = first; phase < last; ++phase) {
+        hipError_t e = launch_random_pass(a, h->p.n_clusters, phase, h->p.seed, grid, h->stream);
+        if (e != hipSuccess) return dev_err(e, "launch_random_pass");
+    }
+    if (timing) FCM_HIP(hipEventRecord(h->ev[1], h->stream));
+    if ((rc = read_state(h)) != FCM_OK) return rc;
+    if (timing) {
+        float ms = 0.f;
+        FCM_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+        h->kernel_ms += ms;
+    }
+    batch -= last - first;
+    return FCM_OK;
+}
+
 // Run up to `batch` passes and read the state back once.
 int run_batch(fcm_handle* h, int batch) {
     const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
+    if (h->p.init == FCM_INIT_RANDOM_U && h->tun.driver != FCM_DRIVER_HISTOGRAM) {
+        int rc = run_random_start(h, batch);
+        if (rc != FCM_OK) return rc;
+        if (batch < 1 || h->h_state->done) return FCM_OK;
+    }
     if (h->tun.driver == FCM_DRIVER_HISTOGRAM) {
         int rc = ensure_level_ws(h);
         if (rc != FCM_OK) return rc;
@@ -539,6 +579,7 @@ int fcm_set_tuning(fcm_handle* h, const fcm_tuning* t) {
     if (rc != FCM_OK) return rc;
     if (!pass_supported(h->p.n_clusters, h->mclass, t->unroll)) return FCM_EUNSUPPORTED;
     if (t->driver == FCM_DRIVER_PERSISTENT && !h->coop) return FCM_EUNSUPPORTED;
+    if (t->driver == FCM_DRIVER_HISTOGRAM && h->p.init == FCM_INIT_RANDOM_U) return FCM_EINVAL;
     const fcm_tuning old = h->tun;
     h->tun = *t;
     int grid = 1;
@@ -830,6 +871,7 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
         if (offsets[i + 1] <= offsets[i]) return FCM_EINVAL;
         int rc = validate_params(params + i);
         if (rc != FCM_OK) return rc;
+        if (params[i].init == FCM_INIT_RANDOM_U) return FCM_EINVAL;  // single handles only
     }
     fcm_batch* b = new (std::nothrow) fcm_batch();
     if (!b) return FCM_ENOMEM;

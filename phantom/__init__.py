@@ -34,6 +34,7 @@ __all__ = [
     "phantom_3d",
     "counter_u64",
     "uniform01",
+    "uniform24",
     "normal01",
     "jittered_params",
     "batch_instances",
@@ -86,6 +87,13 @@ def uniform01(key: int, idx: np.ndarray) -> np.ndarray:
     """Uniform doubles in (0, 1] with 53 random bits."""
     h = counter_u64(key, idx)
     return ((h >> np.uint64(11)).astype(np.float64) + 1.0) * (1.0 / 9007199254740992.0)
+
+
+def uniform24(key: int, idx: np.ndarray) -> np.ndarray:
+    """Uniform values in (0, 1] with 24 random bits, (top 24 bits + 1) / 2^24:
+    exact in FP32 and FP64 alike."""
+    h = counter_u64(key, idx)
+    return ((h >> np.uint64(40)).astype(np.float64) + 1.0) * (1.0 / 16777216.0)
 
 
 def normal01(key: int, idx: np.ndarray) -> np.ndarray:

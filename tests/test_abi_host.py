@@ -175,3 +175,10 @@ def test_quality_validation(lib):
     assert lib.fcm_dice(FAKE, 4, 4, bad, FAKE, None) == L.FCM_EINVAL
     bad = (i32 * 4)(0, -2, 1, 2)
     assert lib.fcm_dice(FAKE, 4, 4, bad, FAKE, None) == L.FCM_EINVAL
+
+
+def test_random_start_is_single_handle_only(lib):
+    recs = (L.FcmParams * 2)(_params(), _params(init=L.FCM_INIT_RANDOM_U, seed=5))
+    off = (ctypes.c_int64 * 3)(0, 100, 250)
+    b = ctypes.c_void_p()
+    assert lib.fcm_batch_init(ctypes.byref(b), FAKE, off, 2, recs, None) == L.FCM_EINVAL

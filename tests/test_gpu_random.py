@@ -1,0 +1,164 @@
+"""GPU parity of the paper's own start (Sec. 2.1, Algorithm 1 as printed):
+random memberships U^0 from the SplitMix64 stream, centroids first, the
+paper's eps = 0.005.  The GPU draws U^0 itself; the oracle takes the same
+weights from the input generator and normalises them in FP64."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import fcm_hist, fcm_ref
+from phantom import PhantomParams, phantom, phantom_2d, uniform24
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+EPS_PAPER = 0.005
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1601_00072_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def announce(*what):
+    print("CASE", *what, flush=True)
+
+
+def weights(seed, n, C):
+    return uniform24(seed, np.arange(n * C, dtype=np.uint64)).reshape(n, C)
+
+
+def run_gpu(torch_dev, x_np, C, m, eps, seed, driver, offset=0, max_iter=300, steps=None):
+    torch, dev = torch_dev
+    from paper_1601_00072_amd import FCM
+    flat = np.ascontiguousarray(x_np).ravel()
+    buf = torch.zeros(flat.size + offset + 16, dtype=torch.uint8, device=dev)
+    buf[offset:offset + flat.size] = torch.from_numpy(flat).to(dev)
+    x = buf[offset:offset + flat.size]
+    with FCM(x, C, m=m, eps=eps, max_iter=max_iter, init=("random_u", seed)) as f:
+        f.set_tuning(driver=driver)
+        if steps:
+            res = None
+            for _ in range(max_iter + 2):
+                res = f.iterate(steps)
+                if res.status != 2:
+                    break
+        else:
+            res = f.solve()
+        traj = P.gpu_trajectory(f, res.iters)
+        lab = f.labels().cpu().numpy()
+    return res, traj, lab
+
+
+@dataclasses.dataclass
+class _Res:
+    iters: int
+
+
+def shifted(tr):
+    """The trajectory from v^1 on, re-indexed from 0 (the centroid-first
+    iteration that follows the first update); delta^1 is checked apart."""
+    return fcm_ref.Trajectory(v=tr.v[1:], delta=[float("nan")] + list(tr.delta[2:]), J=tr.J[1:], T=tr.T - 1,
+                              status=tr.status)
+
+
+def check(x, C, m, eps, seed, res, traj, lab, max_iter=300):
+    r = weights(seed, np.asarray(x).size, C)
+    ora = fcm_ref.solve_random_u(x, C, m, eps, max_iter, r)
+    hist = fcm_hist.histogram(x)
+    vs, ds, Js = traj
+    # pass 0: nothing but v^1 is defined
+    assert np.all(np.isnan(vs[0])) and np.isnan(ds[0]) and np.isnan(Js[0])
+    assert res.status in (0, 1) and res.iters >= 1
+    T_ora = ora.T
+    if res.iters != T_ora:
+        ora = fcm_ref.solve_random_u(x, C, m, 0.0, max(res.iters, T_ora) + 1, r)
+    osh = shifted(ora)
+    if res.iters != T_ora:
+        P.check_iterations(_Res(res.iters - 1), T_ora - 1, osh, eps, hist=hist, m=m, gpu_vs=vs[1:])
+    gsh = (vs[1:], [float("nan")] + list(ds[2:]), Js[1:])
+    err = P.compare(_Res(res.iters - 1), gsh, osh, eps, hist=hist, m=m)
+    # delta^1 against the random U^0: the FP32 draw normalisation is within the
+    # fixed terms; the centroid difference at v^1 propagates as for any pass
+    bd = P.Bounds(hist, m, osh, vs[1:])
+    e1 = bd.err(0)
+    tol = P.D_ABS + P.D_REL * ora.delta[1] + bd.sens(0) * e1
+    assert abs(ds[1] - ora.delta[1]) <= tol, (ds[1], ora.delta[1], tol)
+    amb = P.check_labels(x, lab, ora.v[res.iters])
+    assert res.passes == res.iters + 1
+    return ora, err, amb
+
+
+@pytest.mark.parametrize("driver", [0, 1, 2])
+@pytest.mark.parametrize("C,m", [(4, 2.0), (2, 2.0), (7, 1.5), (3, 2.5)])
+def test_paper_protocol_slice(torch_dev, driver, C, m):
+    announce("random start slice 200x200 driver", driver, "C", C, "m", m)
+    x = phantom_2d(200, 200, seed=1)
+    seed = 1000 + C
+    res, traj, lab = run_gpu(torch_dev, x, C, m, EPS_PAPER, seed, driver)
+    ora, err, amb = check(x, C, m, EPS_PAPER, seed, res, traj, lab)
+    print("T", res.iters, "oracle T", ora.T, "errors", err, flush=True)
+
+
+@pytest.mark.parametrize("offset", [1, 7])
+def test_paper_protocol_volume_unaligned(torch_dev, offset):
+    announce("random start volume 40x96x96 offset", offset)
+    x = phantom(PhantomParams(shape=(40, 96, 96), seed=6))
+    res, traj, lab = run_gpu(torch_dev, x, 4, 2.0, EPS_PAPER, 77, 2, offset=offset)
+    check(x, 4, 2.0, EPS_PAPER, 77, res, traj, lab)
+
+
+@pytest.mark.parametrize("driver", [0, 2])
+def test_paper_protocol_tight_eps(torch_dev, driver):
+    """The same start run to eps = 1e-5: many passes after the random ones."""
+    announce("random start tight eps driver", driver)
+    x = phantom_2d(160, 120, seed=3)
+    res, traj, lab = run_gpu(torch_dev, x, 4, 2.0, 1e-5, 5, driver)
+    check(x, 4, 2.0, 1e-5, 5, res, traj, lab)
+
+
+@pytest.mark.parametrize("driver,steps", [(0, 1), (2, 1), (2, 3), (1, 2)])
+def test_paper_protocol_stepwise(torch_dev, driver, steps):
+    """iterate() in small steps crosses the random passes and the driver's."""
+    announce("random start stepwise driver", driver, "steps", steps)
+    x = phantom_2d(128, 128, seed=4)
+    res, traj, lab = run_gpu(torch_dev, x, 4, 2.0, 1e-4, 11, driver, steps=steps)
+    check(x, 4, 2.0, 1e-4, 11, res, traj, lab)
+
+
+def test_paper_protocol_tiny_and_max_iter(torch_dev):
+    announce("random start tiny inputs")
+    for n in (1, 5, 17, 33):
+        x = np.arange(n, dtype=np.uint8) * 7
+        res, traj, lab = run_gpu(torch_dev, x, 3, 2.0, EPS_PAPER, n, 0)
+        ora = fcm_ref.solve_random_u(x, 3, 2.0, EPS_PAPER, 300, weights(n, n, 3))
+        assert np.allclose(traj[0][1], ora.v[1], rtol=1e-5, atol=1e-4), (n, traj[0][1], ora.v[1])
+    x = phantom_2d(96, 96, seed=9)
+    res, traj, lab = run_gpu(torch_dev, x, 6, 2.0, 1e-9, 3, 2, max_iter=1)
+    assert res.iters == 1 and res.status == 1
+    ora = fcm_ref.solve_random_u(x, 6, 2.0, 1e-9, 1, weights(3, x.size, 6))
+    assert np.allclose(res.centroids, ora.v[1], rtol=1e-5)
+
+
+def test_seed_changes_start(torch_dev):
+    announce("random start seeds")
+    x = phantom_2d(64, 64, seed=2)
+    a = run_gpu(torch_dev, x, 4, 2.0, EPS_PAPER, 1, 2)[1][0][1]
+    b = run_gpu(torch_dev, x, 4, 2.0, EPS_PAPER, 2, 2)[1][0][1]
+    c = run_gpu(torch_dev, x, 4, 2.0, EPS_PAPER, 1, 2)[1][0][1]
+    assert not np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_rejected_with_histogram_driver(torch_dev):
+    torch, dev = torch_dev
+    from paper_1601_00072_amd import FCM, FcmError
+    x = torch.zeros(100, dtype=torch.uint8, device=dev)
+    with FCM(x, 2, init=("random_u", 1)) as f:
+        with pytest.raises(FcmError):
+            f.set_tuning(driver=3)
