@@ -274,6 +274,30 @@ def paper_protocol(dev, x, shape):
                          "centroids": [round(float(v), 4) for v in r.centroids]}}
 
 
+def paper_design(dev, x, shape, fused_ms, eps):
+    """The paper's GPU structure (per-cluster kernels, Algorithm 2 reductions,
+    U copied to the host every iteration for the stopping test) on the
+    headline volume, against the fused persistent solve of the same start."""
+    import torch
+
+    from paper_1601_00072_amd import paper_baseline
+    out = {}
+    for name, init, e in (("linspace start, eps=%g" % eps, None, eps), ("random U^0 seed 3, eps=0.005", ("random_u", 3), 0.005)):
+        paper_baseline(x, 4, eps=e, init=init)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            res, _, _, st = paper_baseline(x, 4, eps=e, init=init)
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        out[name] = {"iterations": res.iters, "ms_per_solve": ms, "loop_ms": st["total_ms"],
+                     "kernels_ms": st["kernels_ms"], "copy_ms": st["copy_ms"], "host_test_ms": st["host_ms"],
+                     "launches": st["launches"]}
+    out["fused_persistent_ms_same_start"] = fused_ms
+    out["speedup_fused_vs_paper_design"] = out["linspace start, eps=%g" % eps]["ms_per_solve"] / fused_ms
+    return out
+
+
 def quality(dev, shape, seed):
     """Dice coefficient per tissue (Eq.5) of the GPU segmentation of the
     headline volume and of the 512x512x256 volume against the phantoms'
@@ -555,8 +579,10 @@ def main():
         print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
         pp = paper_protocol(dev, x, shape)
         print(f"# paper protocol: {pp}", file=sys.stderr, flush=True)
+        pd = paper_design(dev, x, shape, ms_per_step, eps)
+        print(f"# paper design: {pd}", file=sys.stderr, flush=True)
         out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
-                        "segmentation_quality": q, "paper_protocol": pp}
+                        "segmentation_quality": q, "paper_protocol": pp, "paper_design_baseline": pd}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -362,6 +362,33 @@ int fcm_confusion(const uint8_t* d_pred, const uint8_t* d_truth, int64_t n, int3
 int fcm_dice(const uint64_t* d_counts, int32_t n_pred, int32_t n_truth, const int32_t* class_of, double* d_dsc,
              void* stream);
 
+/* ---- the paper's GPU design, as a baseline (Sec. 4) -------------------------- */
+
+typedef struct fcm_paper_stats {
+    double  total_ms;    /* the iteration loop, host wall clock */
+    double  kernels_ms;  /* device time of the per-cluster kernels (HIP events) */
+    double  copy_ms;     /* device-to-host copies of U and v after each iteration */
+    double  host_ms;     /* the host's stopping tests */
+    int64_t launches;    /* kernel launches in the loop (5 C per iteration) */
+} fcm_paper_stats;
+
+/* Solve with the structure the paper gives its GPU implementation (Sec. 4):
+ * U (C x n, FP32) in device memory; per iteration and cluster a per-pixel
+ * kernel for the Eq.3 terms, two Algorithm 2 reductions (128 threads per
+ * block, n / 256 partial sums), a one-thread kernel for the final sums (FP64)
+ * and the centroid; per cluster a per-pixel Eq.4 kernel; then U is copied to
+ * the host, which tests max |U^t - U^(t-1)| < eps.  Defuzzification on the
+ * host.  Starts: FCM_INIT_RANDOM_U (the paper's: U^0 drawn on the host from
+ * the same SplitMix64 stream as the fused solver's), FCM_INIT_LINSPACE or
+ * FCM_INIT_GIVEN (U^0 = Eq.4 at v^0).  d_x: n device bytes.  Host outputs, each
+ * may be NULL: v_hist[(max_iter + 1) * C] (v^t for t = 0..T; v^0 NaN for the
+ * random start), delta_hist[max_iter + 1] (delta^t, delta^0 NaN), labels[n].
+ * out->J is NaN (the design computes no objective).  Allocates and frees its
+ * own buffers (U on the device, two pinned host copies of U); synchronous.
+ * A baseline for measurement, not a fast path. */
+int fcm_paper_solve(const uint8_t* d_x, int64_t n, const fcm_params* p, void* stream, fcm_result* out,
+                    double* v_hist, double* delta_hist, uint8_t* labels, fcm_paper_stats* stats);
+
 /* Static description of a status code, and the last HIP error text of this thread. */
 const char* fcm_strerror(int status);
 const char* fcm_last_error(void);

@@ -3,6 +3,6 @@
 PyTorch supplies device memory and streams; every step of the iteration runs
 in the library's HIP kernels.
 """
-from .api import FCM, MLP, FCMBatch, FcmError, Result, confusion, dice, histogram, rank_classes, solve
+from .api import FCM, MLP, FCMBatch, FcmError, Result, confusion, dice, histogram, paper_baseline, rank_classes, solve
 
-__all__ = ["FCM", "FCMBatch", "MLP", "FcmError", "Result", "confusion", "dice", "histogram", "rank_classes", "solve"]
+__all__ = ["FCM", "FCMBatch", "MLP", "FcmError", "Result", "confusion", "dice", "histogram", "paper_baseline", "rank_classes", "solve"]

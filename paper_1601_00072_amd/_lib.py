@@ -48,7 +48,7 @@ EXPORTS = (
     "fcm_batch_destroy", "fcm_mlp_param_count", "fcm_mlp_create", "fcm_mlp_get_params", "fcm_mlp_set_params",
     "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
-    "fcm_confusion", "fcm_dice",
+    "fcm_confusion", "fcm_dice", "fcm_paper_solve",
 )
 
 
@@ -89,6 +89,16 @@ class FcmResult(ctypes.Structure):
         ("kernel_ms", ctypes.c_double),
         ("lo", ctypes.c_int32),
         ("hi", ctypes.c_int32),
+    ]
+
+
+class FcmPaperStats(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double),
+        ("kernels_ms", ctypes.c_double),
+        ("copy_ms", ctypes.c_double),
+        ("host_ms", ctypes.c_double),
+        ("launches", ctypes.c_int64),
     ]
 
 
@@ -177,6 +187,9 @@ def load() -> ctypes.CDLL:
     lib.fcm_mlp_destroy.restype = None
     lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
     lib.fcm_histogram.restype = ctypes.c_int
+    lib.fcm_paper_solve.argtypes = [vp, i64, ctypes.POINTER(FcmParams), vp, ctypes.POINTER(FcmResult), vp, vp, vp,
+                                    ctypes.POINTER(FcmPaperStats)]
+    lib.fcm_paper_solve.restype = ctypes.c_int
     lib.fcm_confusion.argtypes = [vp, vp, i64, i32, i32, vp, vp]
     lib.fcm_confusion.restype = ctypes.c_int
     lib.fcm_dice.argtypes = [vp, i32, i32, ctypes.POINTER(i32), vp, vp]

@@ -358,6 +358,46 @@ def histogram(x, sizes, stream=None):
     return out
 
 
+def paper_baseline(x, n_clusters: int, m: float = 2.0, eps: float = 0.005, max_iter: int = 300, init=None,
+                   labels: bool = False, stream=None):
+    """Solve with the paper's own GPU structure (fcm_paper_solve): per-cluster
+    kernels, Algorithm 2 reductions, U copied to the host every iteration for
+    the stopping test.  init: None (evenly spaced), C centroids, or
+    ("random_u", seed).  Returns (Result, trajectory dict with "v" [T+1][C]
+    and "delta" [T+1], host labels or None, stats dict)."""
+    import torch
+    lib = L.load()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.uint8 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous uint8 device tensor")
+    C = int(n_clusters)
+    seed, ptr, keep = 0, None, None
+    if init is None:
+        mode = L.FCM_INIT_LINSPACE
+    elif isinstance(init, tuple) and len(init) == 2 and init[0] == "random_u":
+        mode, seed = L.FCM_INIT_RANDOM_U, int(init[1]) & ((1 << 64) - 1)
+    else:
+        v = [float(a) for a in init]
+        if len(v) != C:
+            raise ValueError("init must hold n_clusters values")
+        keep = (ctypes.c_double * C)(*v)
+        mode, ptr = L.FCM_INIT_GIVEN, ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    p = L.FcmParams(n_clusters=C, m=float(m), eps=float(eps), max_iter=int(max_iter), init=mode,
+                    init_centroids=ptr, flags=0, seed=seed)
+    vh = np.full((int(max_iter) + 1, C), np.nan)
+    dh = np.full(int(max_iter) + 1, np.nan)
+    lab = np.empty(x.numel(), dtype=np.uint8) if labels else None
+    r, st = L.FcmResult(), L.FcmPaperStats()
+    rc = lib.fcm_paper_solve(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.byref(p), _stream_handle(stream, x.device),
+                             ctypes.byref(r), vh.ctypes.data_as(ctypes.c_void_p), dh.ctypes.data_as(ctypes.c_void_p),
+                             None if lab is None else lab.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+    if rc < 0:
+        raise FcmError(rc, "fcm_paper_solve")
+    res = _result(r)
+    traj = {"v": vh[:res.iters + 1], "delta": dh[:res.iters + 1]}
+    stats = {f: getattr(st, f) for f, _ in L.FcmPaperStats._fields_}
+    return res, traj, lab, stats
+
+
 def confusion(pred, truth, n_pred: int, n_truth: int, stream=None):
     """Confusion counts of two uint8 label tensors on the device (Sec. 5.2.2):
     an int64 device tensor [n_pred * n_truth + 1]; entry j * n_truth + k counts

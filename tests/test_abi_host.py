@@ -182,3 +182,17 @@ def test_random_start_is_single_handle_only(lib):
     off = (ctypes.c_int64 * 3)(0, 100, 250)
     b = ctypes.c_void_p()
     assert lib.fcm_batch_init(ctypes.byref(b), FAKE, off, 2, recs, None) == L.FCM_EINVAL
+
+
+def test_paper_baseline_validation(lib):
+    r = L.FcmResult()
+    p = _params()
+    assert lib.fcm_paper_solve(None, 100, ctypes.byref(p), None, ctypes.byref(r), None, None, None, None) == L.FCM_EINVAL
+    assert lib.fcm_paper_solve(FAKE, 0, ctypes.byref(p), None, ctypes.byref(r), None, None, None, None) == L.FCM_EINVAL
+    assert lib.fcm_paper_solve(FAKE, 100, None, None, ctypes.byref(r), None, None, None, None) == L.FCM_EINVAL
+    assert lib.fcm_paper_solve(FAKE, 100, ctypes.byref(p), None, None, None, None, None, None) == L.FCM_EINVAL
+    for kw in (dict(init=L.FCM_INIT_DEVICE), dict(n_clusters=9), dict(m=1.0), dict(eps=0.0), dict(max_iter=0),
+               dict(init=L.FCM_INIT_GIVEN)):
+        q = _params(**kw)
+        assert lib.fcm_paper_solve(FAKE, 100, ctypes.byref(q), None, ctypes.byref(r), None, None, None,
+                                   None) == L.FCM_EINVAL, kw
