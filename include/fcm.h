@@ -168,6 +168,24 @@ int fcm_solve(fcm_handle* h, fcm_result* out);
  * d_labels: caller-owned device buffer of n bytes.  Enqueued, not waited for. */
 int fcm_labels(fcm_handle* h, uint8_t* d_labels);
 
+/* Enqueue a whole solve (reset, start, Algorithm 1 to its end) on the
+ * handle's stream and return without waiting: with the persistent driver this
+ * is one kernel launch and no host synchronisation, so that solves, label
+ * launches and other work can follow back to back (serving loops, pipelines).
+ * With the other drivers, or the random-membership start, whose passes are
+ * driven from the host, it runs the synchronous solve.  The result is read
+ * with fcm_result; labels and trajectories may be requested meanwhile (they
+ * are ordered on the same stream).  A wait that hits its time limit in any
+ * pending solve is reported by the next fcm_solve_wait. */
+int fcm_solve_async(fcm_handle* h);
+
+/* Wait for the handle's stream and report the last solve (as fcm_solve
+ * does).  out->kernel_ms: with FCM_F_TIMING, the summed launch time of every
+ * solve since the previous fcm_solve_wait.  total_passes (may be NULL): fused
+ * passes committed on this handle since it was created (all drivers; restarts
+ * from 0 after a recovered time-out), to count the work of pending solves. */
+int fcm_solve_wait(fcm_handle* h, fcm_result* out, int64_t* total_passes);
+
 /* Copy v^T (C doubles) to the host buffer out. */
 int fcm_centroids(fcm_handle* h, double* out);
 

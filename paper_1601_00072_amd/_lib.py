@@ -48,7 +48,7 @@ EXPORTS = (
     "fcm_batch_destroy", "fcm_mlp_param_count", "fcm_mlp_create", "fcm_mlp_get_params", "fcm_mlp_set_params",
     "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
-    "fcm_confusion", "fcm_dice", "fcm_paper_solve",
+    "fcm_confusion", "fcm_dice", "fcm_paper_solve", "fcm_solve_async", "fcm_solve_wait",
 )
 
 
@@ -190,6 +190,10 @@ def load() -> ctypes.CDLL:
     lib.fcm_paper_solve.argtypes = [vp, i64, ctypes.POINTER(FcmParams), vp, ctypes.POINTER(FcmResult), vp, vp, vp,
                                     ctypes.POINTER(FcmPaperStats)]
     lib.fcm_paper_solve.restype = ctypes.c_int
+    lib.fcm_solve_async.argtypes = [vp]
+    lib.fcm_solve_async.restype = ctypes.c_int
+    lib.fcm_solve_wait.argtypes = [vp, ctypes.POINTER(FcmResult), ctypes.POINTER(i64)]
+    lib.fcm_solve_wait.restype = ctypes.c_int
     lib.fcm_confusion.argtypes = [vp, vp, i64, i32, i32, vp, vp]
     lib.fcm_confusion.restype = ctypes.c_int
     lib.fcm_dice.argtypes = [vp, i32, i32, ctypes.POINTER(i32), vp, vp]

@@ -134,6 +134,20 @@ class FCM:
             raise FcmError(rc, "fcm_solve")
         return _result(r)
 
+    def solve_async(self):
+        """Enqueue a whole solve without waiting (fcm_solve_async); read it
+        with result()."""
+        self._check(self._lib.fcm_solve_async(self._h), "fcm_solve_async")
+
+    def result(self):
+        """Wait and report the last solve (fcm_solve_wait); returns (Result, fused
+        passes committed on this handle so far)."""
+        r, tot = L.FcmResult(), ctypes.c_int64()
+        rc = self._lib.fcm_solve_wait(self._h, ctypes.byref(r), ctypes.byref(tot))
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_solve_wait")
+        return _result(r), int(tot.value)
+
     def labels(self, out=None):
         import torch
         if out is None:

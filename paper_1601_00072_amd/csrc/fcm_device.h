@@ -844,6 +844,7 @@ __device__ __forceinline__ void commit(const PassArgs& a, int p, const double* v
     st->J = s.J;
     st->delta = s.delta;
     st->passes = p + 1;
+    st->sync.passes_total += 1;
     if (!s.done) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {

@@ -19,6 +19,7 @@ struct SyncState {
     uint32_t gen;             // last round of the previous cooperative launch
     uint32_t abort;           // set when a wait hit its time limit; every block then exits
     uint64_t bcw[kMaxC + 1];  // block 0's decision: tagged centroids, then (next pass << 1 | done)
+    uint64_t passes_total;    // fused passes committed since the handle was created (every driver)
 };
 
 // Device-resident solver state.  Written only by the last block of a pass (or

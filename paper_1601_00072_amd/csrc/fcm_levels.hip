@@ -166,6 +166,7 @@ __global__ __launch_bounds__(256) void fcm_levels_kernel(LevelArgs a) {
             st->J = r[2 * C];
             st->delta = delta;
             st->passes = p + 1;
+            st->sync.passes_total += 1;
             if (!done) {
                 for (int k = 0; k < C; ++k) {
                     a.hist_v[(int64_t)(p + 1) * C + k] = vnext[k];

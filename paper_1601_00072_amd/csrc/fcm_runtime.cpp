@@ -119,6 +119,8 @@ struct fcm_handle {
 
     std::vector<hipEvent_t> ev;
     double kernel_ms = 0.0;
+    int async_timed = 0;        // timed fcm_solve_async launches since the last fcm_solve_wait (event pairs)
+    double async_ms = 0.0;      // kernel time of host-driven solves run by fcm_solve_async
 
     // warm start workspace (first fcm_solve_warm)
     int64_t* d_woff = nullptr;     // {0, n}
@@ -316,9 +318,27 @@ int run_random_start(fcm_handle* h, int& batch) {
     return FCM_OK;
 }
 
+// Kernel time of the timed asynchronous solves still pending, folded into
+// async_ms (waits for their last event), so that their event pairs can be reused.
+int fold_async(fcm_handle* h) {
+    if (h->async_timed == 0) return FCM_OK;
+    FCM_HIP(hipEventSynchronize(h->ev[2 * h->async_timed - 1]));
+    for (int i = 0; i < h->async_timed; ++i) {
+        float t = 0.f;
+        FCM_HIP(hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1]));
+        h->async_ms += t;
+    }
+    h->async_timed = 0;
+    return FCM_OK;
+}
+
 // Run up to `batch` passes and read the state back once.
 int run_batch(fcm_handle* h, int batch) {
     const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
+    if (timing && h->async_timed) {
+        int rc = fold_async(h);
+        if (rc != FCM_OK) return rc;
+    }
     if (h->p.init == FCM_INIT_RANDOM_U && h->tun.driver != FCM_DRIVER_HISTOGRAM) {
         int rc = run_random_start(h, batch);
         if (rc != FCM_OK) return rc;
@@ -637,6 +657,65 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
         budget -= batch;
     }
     fill_result(h, out);
+    return out->status;
+}
+
+int fcm_solve_async(fcm_handle* h) {
+    if (!h) return FCM_EINVAL;
+    if (h->tun.driver != FCM_DRIVER_PERSISTENT || h->p.init == FCM_INIT_RANDOM_U) {
+        // host-driven solves: the synchronous path
+        fcm_result r;
+        int rc = fold_async(h);
+        if (rc != FCM_OK) return rc;
+        rc = enqueue_start(h);
+        if (rc != FCM_OK) return rc;
+        rc = fcm_solve(h, &r);
+        if (rc < 0) return rc;
+        h->async_ms += r.kernel_ms;
+        return FCM_OK;
+    }
+    // A fresh persistent launch writes every result field of the state itself
+    // (the data-range pass commits the start) and reads none, so the clear
+    // of a reset is skipped unless an abort left the exchange words unknown.
+    if (h->aborted) {
+        int rc = enqueue_start(h);
+        if (rc != FCM_OK) return rc;
+    } else {
+        std::memset(h->h_state, 0, sizeof(DevState));
+        h->h_state->iters = -1;
+        h->h_state->status = FCM_RUNNING;
+        h->kernel_ms = 0.0;
+        h->pending_init = true;
+    }
+    PassArgs a = pass_args(h);
+    a.max_passes = h->p.max_iter + 1;
+    const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
+    if (timing) {
+        int rc = ensure_events(h, 2 * (h->async_timed + 1));
+        if (rc != FCM_OK) return rc;
+        FCM_HIP(hipEventRecord(h->ev[2 * h->async_timed], h->stream));
+    }
+    hipError_t e = launch_persist(a, h->p.n_clusters, h->mclass, h->tun.unroll, h->grid,
+                                  h->tun.launch == FCM_LAUNCH_COOPERATIVE, h->stream);
+    if (e != hipSuccess) return dev_err(e, "persistent launch");
+    h->pending_init = false;
+    if (timing) {
+        FCM_HIP(hipEventRecord(h->ev[2 * h->async_timed + 1], h->stream));
+        ++h->async_timed;
+    }
+    return FCM_OK;
+}
+
+int fcm_solve_wait(fcm_handle* h, fcm_result* out, int64_t* total_passes) {
+    if (!h || !out) return FCM_EINVAL;
+    int rc = h->pending_init ? sync_state(h) : read_state(h);
+    if (rc != FCM_OK) return rc;
+    if ((rc = fold_async(h)) != FCM_OK) return rc;
+    const double ms = h->async_ms;
+    h->async_ms = 0.0;
+    fill_result(h, out);
+    out->kernel_ms = ms > 0.0 ? ms : h->kernel_ms;
+    if (total_passes) *total_passes = (int64_t)h->h_state->sync.passes_total;
     return out->status;
 }
 

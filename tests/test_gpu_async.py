@@ -1,0 +1,97 @@
+"""Asynchronous solves (fcm_solve_async / fcm_solve_wait): back-to-back
+solves without host synchronisation give the synchronous solve's result bit
+for bit, the device pass counter counts every pass, and labels and
+trajectories ordered behind them match."""
+import numpy as np
+import pytest
+
+from phantom import PhantomParams, phantom, phantom_2d
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1601_00072_amd import _lib
+    _lib.load()
+    return torch, torch.device("cuda:0")
+
+
+def announce(*what):
+    print("CASE", *what, flush=True)
+
+
+def same(a, b):
+    assert a.iters == b.iters and a.status == b.status and a.passes == b.passes
+    assert np.array_equal(a.centroids, b.centroids)
+    assert (a.delta == b.delta or (np.isnan(a.delta) and np.isnan(b.delta))) and a.J == b.J
+
+
+@pytest.mark.parametrize("driver", [2, 1, 0])
+@pytest.mark.parametrize("C,m,init", [(4, 2.0, None), (6, 1.5, None), (3, 2.5, [20.0, 90.5, 170.0]),
+                                      (4, 2.0, ("random_u", 9))])
+def test_async_equals_sync(torch_dev, driver, C, m, init):
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCM
+    announce("async driver", driver, "C", C, "m", m, "init", init)
+    x = torch.from_numpy(phantom(PhantomParams(shape=(64, 128, 128), seed=2)).ravel()).to(d)
+    with FCM(x, C, m=m, init=init, timing=True) as f:
+        f.set_tuning(driver=driver)
+        ref = f.solve()
+        lab_ref = f.labels().cpu().numpy()
+        traj_ref = [f.trajectory(t) for t in range(ref.iters + 1)]
+        _, tot0 = f.result()
+        lab = torch.empty_like(x)
+        K = 5
+        for _ in range(K):
+            f.solve_async()
+            f.labels(lab)
+        r, tot = f.result()
+        same(r, ref)
+        assert tot - tot0 == K * ref.passes
+        assert r.kernel_ms > 0.0
+        assert np.array_equal(lab.cpu().numpy(), lab_ref)
+        for t in range(ref.iters + 1):
+            a, b = f.trajectory(t), traj_ref[t]
+            assert np.array_equal(a[0], b[0]) or (np.all(np.isnan(a[0])) and np.all(np.isnan(b[0])))
+
+
+def test_async_mixed_with_sync_calls(torch_dev):
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCM
+    announce("async mixed")
+    x = torch.from_numpy(phantom_2d(256, 256, seed=5).ravel()).to(d)
+    with FCM(x, 5, timing=True) as f:
+        ref = f.solve()
+        f.solve_async()
+        f.solve_async()
+        f.reset()
+        r = f.solve()              # a synchronous solve after pending async ones
+        same(r, ref)
+        f.solve_async()
+        r2 = f.iterate(3)          # stepping restarts nothing: the async solve already finished
+        assert r2.iters == ref.iters
+        f.reset()
+        r3 = f.iterate(2)
+        assert r3.iters == 1 and r3.status == 2
+        f.solve_async()            # an async solve replaces the partial one
+        r4, _ = f.result()
+        same(r4, ref)
+
+
+def test_async_many_sizes(torch_dev):
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCM
+    announce("async sizes")
+    for n in (1, 17, 4099, 65536 + 5):
+        rng = np.random.default_rng(n)
+        x = torch.from_numpy(rng.integers(0, 256, n).astype(np.uint8)).to(d)
+        with FCM(x, 3) as f:
+            ref = f.solve()
+            for _ in range(3):
+                f.solve_async()
+            r, _ = f.result()
+            same(r, ref)
