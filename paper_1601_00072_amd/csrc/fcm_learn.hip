@@ -114,16 +114,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const float* A, const float* 
     const int row0 = blockIdx.y * kT, col0 = blockIdx.x * kT;
     float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
     for (int k0 = 0; k0 < K; k0 += kT) {
+        // consecutive threads take consecutive addresses of the stored
+        // layout (transposed operands walk the tile the other way round)
         for (int e = threadIdx.x; e < kT * kT; e += 256) {
-            const int r = e / kT, c = e % kT;
+            const int r = TA ? e % kT : e / kT, c = TA ? e / kT : e % kT;  // As[m][k]
             const int gm = row0 + r, gk = k0 + c;
             float va = 0.f;
             if (gm < M && gk < K) va = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
             As[r][c] = va;
-            const int gk2 = k0 + r, gn = col0 + c;
+            const int rb = TB ? e % kT : e / kT, cb = TB ? e / kT : e % kT;  // Bs[k][n]
+            const int gk2 = k0 + rb, gn = col0 + cb;
             float vb = 0.f;
             if (gk2 < K && gn < N) vb = TB ? B[(int64_t)gn * K + gk2] : B[(int64_t)gk2 * N + gn];
-            Bs[r][c] = vb;
+            Bs[rb][cb] = vb;
         }
         __syncthreads();
 #pragma unroll 8
@@ -166,17 +169,31 @@ hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* 
     return hipGetLastError();
 }
 
-// column sums of G [M][N] into out[N] (row order fixed)
-__global__ void colsum_kernel(const float* G, int M, int N, float* out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// column sums of G [M][N] into out[N]: a block takes 16 columns; its 16 row
+// groups (thread (g, c) adds rows g, g + 16, ... of column c) run in
+// parallel, then the groups are added in order g = 0..15 -- a fixed order, so
+// the sums are reproducible run to run
+constexpr int kColTile = 16, kRowGroups = 16;
+
+__global__ __launch_bounds__(kColTile * kRowGroups) void colsum_kernel(const float* G, int M, int N, float* out) {
+    __shared__ float part[kRowGroups][kColTile + 1];
+    const int c = threadIdx.x % kColTile, g = threadIdx.x / kColTile;
+    const int j = blockIdx.x * kColTile + c;
     float s = 0.f;
-    for (int i = 0; i < M; ++i) s += G[(int64_t)i * N + j];
-    out[j] = s;
+    if (j < N)
+        for (int i = g; i < M; i += kRowGroups) s += G[(int64_t)i * N + j];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < N) {
+        float t = part[0][c];
+        for (int r = 1; r < kRowGroups; ++r) t += part[r][c];
+        out[j] = t;
+    }
 }
 
 hipError_t launch_colsum(const float* G, int M, int N, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 127) / 128), dim3(128), 0, s, G, M, N, out);
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + kColTile - 1) / kColTile), dim3(kColTile * kRowGroups), 0, s, G, M, N,
+                       out);
     return hipGetLastError();
 }
 
