@@ -135,16 +135,15 @@ def timed_solves(f, steps, labels=None):
 
 def timed_async(f, steps, labels):
     """`steps` whole solves, each with its labels, enqueued back to back
-    (fcm_solve_async: one persistent launch per solve, no host wait), then one
-    wait.  Returns (seconds, fused passes counted on the device, summed launch
+    (fcm_solve_async: one persistent launch per solve that also writes the
+    labels, no host wait), then one wait.  Returns (seconds, fused passes counted on the device, summed launch
     time in ms, last result)."""
     import torch
     _, tot0 = f.result()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        f.solve_async()
-        f.labels(labels)
+        f.solve_async(labels)
     r, tot = f.result()
     torch.cuda.synchronize()
     return time.perf_counter() - t0, tot - tot0, r.kernel_ms, r
@@ -567,8 +566,8 @@ def main():
             "n_voxels": n, "C": C, "m": m, "eps": eps, "iterations": r.iters,
             "passes_per_solve": passes_per_solve,
             "time_to_converge_ms": ms_per_step,
-            "step": "data-range pass + fused passes to convergence + labels (one persistent launch + labels), "
-                    "steps enqueued back to back (fcm_solve_async), one host wait for the timed run; "
+            "step": "data-range pass + fused passes to convergence + labels, one persistent launch per step "
+                    "(fcm_solve_async), steps enqueued back to back, one host wait for the timed run; "
                     "passes counted on the device",
             "ms_per_step_host_waits_each_solve": el_sync * 1e3 / args.steps,
             "value_host_waits_each_solve": n * passes_sync / el_sync,

@@ -170,14 +170,17 @@ int fcm_labels(fcm_handle* h, uint8_t* d_labels);
 
 /* Enqueue a whole solve (reset, start, Algorithm 1 to its end) on the
  * handle's stream and return without waiting: with the persistent driver this
- * is one kernel launch and no host synchronisation, so that solves, label
- * launches and other work can follow back to back (serving loops, pipelines).
- * With the other drivers, or the random-membership start, whose passes are
- * driven from the host, it runs the synchronous solve.  The result is read
- * with fcm_result; labels and trajectories may be requested meanwhile (they
- * are ordered on the same stream).  A wait that hits its time limit in any
- * pending solve is reported by the next fcm_solve_wait. */
-int fcm_solve_async(fcm_handle* h);
+ * is one kernel launch and no host synchronisation, so that solves and other
+ * work can follow back to back (serving loops, pipelines).  d_labels (device,
+ * n bytes, may be NULL): the labels of the result (as fcm_labels writes
+ * them), computed by the same launch once the solve ends.  With the other
+ * drivers, or the random-membership start, whose passes are driven from the
+ * host, it runs the synchronous solve (and fcm_labels).  The result is read
+ * with fcm_solve_wait; trajectories may be requested meanwhile (they are
+ * ordered on the same stream).  A wait that hits its time limit in any
+ * pending solve is reported by the next fcm_solve_wait (the labels of that
+ * solve are then not written). */
+int fcm_solve_async(fcm_handle* h, uint8_t* d_labels);
 
 /* Wait for the handle's stream and report the last solve (as fcm_solve
  * does).  out->kernel_ms: with FCM_F_TIMING, the summed launch time of every

@@ -190,7 +190,7 @@ def load() -> ctypes.CDLL:
     lib.fcm_paper_solve.argtypes = [vp, i64, ctypes.POINTER(FcmParams), vp, ctypes.POINTER(FcmResult), vp, vp, vp,
                                     ctypes.POINTER(FcmPaperStats)]
     lib.fcm_paper_solve.restype = ctypes.c_int
-    lib.fcm_solve_async.argtypes = [vp]
+    lib.fcm_solve_async.argtypes = [vp, vp]
     lib.fcm_solve_async.restype = ctypes.c_int
     lib.fcm_solve_wait.argtypes = [vp, ctypes.POINTER(FcmResult), ctypes.POINTER(i64)]
     lib.fcm_solve_wait.restype = ctypes.c_int

@@ -134,10 +134,18 @@ class FCM:
             raise FcmError(rc, "fcm_solve")
         return _result(r)
 
-    def solve_async(self):
-        """Enqueue a whole solve without waiting (fcm_solve_async); read it
-        with result()."""
-        self._check(self._lib.fcm_solve_async(self._h), "fcm_solve_async")
+    def solve_async(self, labels=None):
+        """Enqueue a whole solve without waiting (fcm_solve_async); with
+        `labels` (a uint8 device tensor of the input's size) the same launch
+        also writes the labels of the result.  Read the result with result()."""
+        import torch
+        ptr = None
+        if labels is not None:
+            if labels.dtype != torch.uint8 or not labels.is_cuda or labels.numel() != self.n or \
+                    not labels.is_contiguous():
+                raise ValueError("labels must be a contiguous uint8 device tensor of the input's size")
+            ptr = ctypes.c_void_p(labels.data_ptr())
+        self._check(self._lib.fcm_solve_async(self._h, ptr), "fcm_solve_async")
 
     def result(self):
         """Wait and report the last solve (fcm_solve_wait); returns (Result, fused

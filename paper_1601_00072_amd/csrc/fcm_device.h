@@ -1032,6 +1032,66 @@ __device__ __forceinline__ void commit_start(DevState* st, double* hist_v, int C
 }
 
 // ---------------------------------------------------------------------------
+// defuzzification inside the solve
+// ---------------------------------------------------------------------------
+
+// LUT[g] = argmin_j |g - v_j| in FP64, ties to the lowest j (the nearest
+// centroid is the cluster of maximal membership for m > 1).
+__device__ __forceinline__ void label_table(const double* v, int C, uint8_t* lut) {
+    for (int g = threadIdx.x; g < 256; g += kBlock) {
+        int best = 0;
+        double bd = fabs((double)g - v[0]);
+        for (int k = 1; k < C; ++k) {
+            const double d = fabs((double)g - v[k]);
+            if (d < bd) {
+                bd = d;
+                best = k;
+            }
+        }
+        lut[g] = (uint8_t)best;
+    }
+}
+
+__device__ __forceinline__ uint4 label_chunk(uint4 w, const uint8_t* lut) {
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t x = words[i];
+        o[i] = (uint32_t)lut[x & 0xFFu] | ((uint32_t)lut[(x >> 8) & 0xFFu] << 8) |
+               ((uint32_t)lut[(x >> 16) & 0xFFu] << 16) | ((uint32_t)lut[x >> 24] << 24);
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// Labels of every voxel of the launch's share (grid-stride chunks; the
+// thread's resident chunk from registers), head and tail by block 0.
+__device__ __forceinline__ void write_labels(const PassArgs& a, const uint8_t* lut, bool resident, uint4 mine) {
+    const int tid = threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + tid;
+    if (a.labels_bytewise) {
+        for (int64_t i = gt; i < a.n; i += stride) a.labels[i] = lut[a.x[i]];
+        return;
+    }
+    const uint4* in = reinterpret_cast<const uint4*>(a.x + a.head);
+    uint4* out = reinterpret_cast<uint4*>(a.labels + a.head);
+    if (resident) {
+        if (gt < a.nbody) out[gt] = label_chunk(mine, lut);
+    } else {
+        for (int64_t c = gt; c < a.nbody; c += stride) out[c] = label_chunk(in[c], lut);
+    }
+    if (blockIdx.x == 0) {
+        const int64_t tail0 = a.head + 16 * a.nbody;
+        const int64_t nr = a.head + (a.n - tail0);
+        if (tid < nr) {
+            const int64_t i = tid < a.head ? (int64_t)tid : tail0 + (tid - a.head);
+            a.labels[i] = lut[a.x[i]];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // driver 2: one cooperative launch per solve
 // ---------------------------------------------------------------------------
 
@@ -1210,6 +1270,16 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 Step<C> s;
                 decide<C>(s_r, p, vcur, a.eps, a.max_iter, s);
                 if (leader) commit<C>(a, p, vcur, s);
+                if (s.done && a.labels && !a.allgather) {
+                    // the result in FP64 for the other blocks' label tables,
+                    // tagged like the decision (which is stored after it)
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        const uint64_t bits = __builtin_bit_cast(uint64_t, vcur[k]);
+                        store_tagged(sy->fin + 2 * k, round, (uint32_t)bits);
+                        store_tagged(sy->fin + 2 * k + 1, round, (uint32_t)(bits >> 32));
+                    }
+                }
                 if (!s.done) {
 #pragma unroll
                     for (int k = 0; k < C; ++k) {
@@ -1235,11 +1305,25 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 }
                 s_p = pn;
             }
+            if (s_ok && done && a.labels) {
+                uint32_t raw[2 * C];
+                s_ok = poll_tagged<2 * C>(sy->fin, round, raw, sy, wall_clock64(), a.spin_ticks);
+#pragma unroll
+                for (int k = 0; k < C; ++k)
+                    s_v64[k] = __builtin_bit_cast(double, (uint64_t)raw[2 * k] | ((uint64_t)raw[2 * k + 1] << 32));
+            }
         }
         __syncthreads();
         if (!leader && !a.allgather && !s_ok) return;
     }
     if (leader && tid == 0) sy->gen = round;
+    if (a.labels && s_done) {
+        // v^T is in s_v64 in every block (its own decision, or block 0's)
+        __shared__ uint8_t s_lut[256];
+        label_table(s_v64, C, s_lut);
+        __syncthreads();
+        write_labels(a, s_lut, resident, mine);
+    }
 }
 
 }  // namespace fcm

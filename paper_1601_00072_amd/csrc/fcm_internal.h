@@ -20,6 +20,7 @@ struct SyncState {
     uint32_t abort;           // set when a wait hit its time limit; every block then exits
     uint64_t bcw[kMaxC + 1];  // block 0's decision: tagged centroids, then (next pass << 1 | done)
     uint64_t passes_total;    // fused passes committed since the handle was created (every driver)
+    uint64_t fin[2 * kMaxC];  // block 0's final centroids in FP64, two tagged halves each (fused labels)
 };
 
 // Device-resident solver state.  Written only by the last block of a pass (or
@@ -86,6 +87,9 @@ struct PassArgs {
     const uint16_t* mlp_w; // mode 3: BF16 parameters of the histogram -> centroid network (C outputs)
     uint32_t* ghist;       // mode 3: [kHistCopies][256] grey-level counters, zero at entry
     uint32_t* ghist_next;  // mode 3: the counters of the next learned launch, zeroed by this one
+    uint8_t* labels;       // persistent launch: labels of the result, written when the solve ends (or null)
+    int32_t labels_bytewise;  // x and labels differ in 16-byte alignment
+    int32_t pad3;
 };
 
 constexpr int kHistCopies = 16;  // copies of the in-kernel histogram (blocks spread their atomics)

@@ -660,7 +660,7 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
     return out->status;
 }
 
-int fcm_solve_async(fcm_handle* h) {
+int fcm_solve_async(fcm_handle* h, uint8_t* d_labels) {
     if (!h) return FCM_EINVAL;
     if (h->tun.driver != FCM_DRIVER_PERSISTENT || h->p.init == FCM_INIT_RANDOM_U) {
         // host-driven solves: the synchronous path
@@ -670,9 +670,9 @@ int fcm_solve_async(fcm_handle* h) {
         rc = enqueue_start(h);
         if (rc != FCM_OK) return rc;
         rc = fcm_solve(h, &r);
-        if (rc < 0) return rc;
+        if (rc < 0 && rc != FCM_ENUMERIC) return rc;
         h->async_ms += r.kernel_ms;
-        return FCM_OK;
+        return d_labels ? fcm_labels(h, d_labels) : FCM_OK;
     }
     // A fresh persistent launch writes every result field of the state itself
     // (the data-range pass commits the start) and reads none, so the clear
@@ -688,7 +688,9 @@ int fcm_solve_async(fcm_handle* h) {
         h->pending_init = true;
     }
     PassArgs a = pass_args(h);
-    a.max_passes = h->p.max_iter + 1;
+    a.max_passes = h->p.max_iter + 1;  // always enough: the launch ends the solve
+    a.labels = d_labels;
+    a.labels_bytewise = (((uintptr_t)h->d_x ^ (uintptr_t)d_labels) & 15) ? 1 : 0;
     const bool timing = (h->p.flags & FCM_F_TIMING) != 0;
     if (timing) {
         int rc = ensure_events(h, 2 * (h->async_timed + 1));

@@ -100,7 +100,7 @@ def test_null_handle_calls(lib):
     assert lib.fcm_trajectory(None, 0, buf, None, None) == L.FCM_EINVAL
     assert lib.fcm_set_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
     assert lib.fcm_get_tuning(None, ctypes.byref(t)) == L.FCM_EINVAL
-    assert lib.fcm_solve_async(None) == L.FCM_EINVAL
+    assert lib.fcm_solve_async(None, None) == L.FCM_EINVAL
     assert lib.fcm_solve_wait(None, ctypes.byref(r), None) == L.FCM_EINVAL
     lib.fcm_destroy(None)
 

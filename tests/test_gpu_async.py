@@ -47,8 +47,7 @@ def test_async_equals_sync(torch_dev, driver, C, m, init):
         lab = torch.empty_like(x)
         K = 5
         for _ in range(K):
-            f.solve_async()
-            f.labels(lab)
+            f.solve_async(lab)
         r, tot = f.result()
         same(r, ref)
         assert tot - tot0 == K * ref.passes
@@ -95,3 +94,32 @@ def test_async_many_sizes(torch_dev):
                 f.solve_async()
             r, _ = f.result()
             same(r, ref)
+
+
+@pytest.mark.parametrize("exchange", [1, 2])
+@pytest.mark.parametrize("grid", [0, 8])
+@pytest.mark.parametrize("x_off,lab_off", [(0, 0), (5, 5), (0, 3), (7, 1)])
+def test_fused_labels(torch_dev, exchange, grid, x_off, lab_off):
+    """Labels written by the solve's own launch equal the labels kernel's,
+    for both exchanges, resident and grid-stride chunks, ragged heads and
+    tails, and label buffers aligned unlike the input (byte path)."""
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCM
+    announce("fused labels exchange", exchange, "grid", grid, "offsets", x_off, lab_off)
+    img = phantom(PhantomParams(shape=(40, 96, 96), seed=8)).ravel()
+    n = img.size - 11
+    buf = torch.zeros(img.size + 32, dtype=torch.uint8, device=d)
+    buf[x_off:x_off + n] = torch.from_numpy(img[:n]).to(d)
+    x = buf[x_off:x_off + n]
+    out = torch.full((n + 32,), 255, dtype=torch.uint8, device=d)
+    lab = out[lab_off:lab_off + n]
+    with FCM(x, 5) as f:
+        f.set_tuning(driver=2, exchange=exchange, grid=grid)
+        ref = f.solve()
+        want = f.labels().cpu().numpy()
+        f.solve_async(lab)
+        r, _ = f.result()
+        same(r, ref)
+        got = out.cpu().numpy()
+        assert np.array_equal(got[lab_off:lab_off + n], want)
+        assert np.all(got[:lab_off] == 255) and np.all(got[lab_off + n:] == 255)  # nothing outside
