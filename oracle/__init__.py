@@ -9,6 +9,8 @@ what the paper and mathematics fix (see ``tests/test_oracle_pins.py``).
 Modules
   fcm_ref    literal Eq.1-Eq.4 / Algorithm 1 per voxel (numpy, FP64)
   fcm_hist   the same sums regrouped over the 256 grey levels (exact regrouping)
+  fcm_fast   the per-voxel iteration in plain C, threaded over the host cores
+             (fcm_fast.c; for timing and large sizes)
   exact      the same iteration in exact rational (m = 2, 3) or 60-digit
              decimal arithmetic, for tiny inputs
   mlp_ref    FP64 forward/backward of the histogram -> centroid network
