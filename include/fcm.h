@@ -87,6 +87,13 @@ extern "C" {
 #define FCM_EXCHANGE_AUTO      0  /* all-gather on small grids, else leader */
 #define FCM_EXCHANGE_LEADER    1  /* block 0 reduces and broadcasts the decision */
 #define FCM_EXCHANGE_ALLGATHER 2  /* every block reduces every partial row itself */
+#define FCM_EXCHANGE_XCD       3  /* two levels: the blocks sharing an XCD (blocks are dealt to
+                                     the 8 XCDs in turn) combine their rows through that XCD's
+                                     L2, one block per XCD publishes an FP64 row, and every
+                                     block adds the 8 XCD rows itself (no broadcast).  The
+                                     dealing is checked in the data-range pass of each solve;
+                                     where it differs, and for launches that continue a solve,
+                                     the leader exchange is used.  Not with FCM_F_KAHAN_ONLY */
 
 /* how the persistent driver launches its kernel */
 #define FCM_LAUNCH_COOPERATIVE 0  /* hipLaunchCooperativeKernel: the runtime guarantees

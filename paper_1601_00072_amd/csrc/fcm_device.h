@@ -316,12 +316,18 @@ struct TaggedRows {
     uint32_t round;
     SyncState* sy;
     uint64_t t0, limit;
+    bool local;  // two-level exchange: the row is read only on this XCD, so it goes to its L2
+    __device__ __forceinline__ void put(int q, uint32_t payload) const {
+        uint64_t* p = W + (size_t)blockIdx.x * S + q;
+        if (local)
+            __hip_atomic_store(p, tagged(round, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            store_tagged(p, round, payload);
+    }
     __device__ __forceinline__ void put_pair(int q, float s, float c) const {
-        store_tagged(W + (size_t)blockIdx.x * S + q, round, __builtin_bit_cast(uint32_t, s - c));
+        put(q, __builtin_bit_cast(uint32_t, s - c));
     }
-    __device__ __forceinline__ void put_max(int q, float m) const {
-        store_tagged(W + (size_t)blockIdx.x * S + q, round, __builtin_bit_cast(uint32_t, m));
-    }
+    __device__ __forceinline__ void put_max(int q, float m) const { put(q, __builtin_bit_cast(uint32_t, m)); }
     template <int R>
     __device__ __forceinline__ bool get(int b, float (&v)[R]) const {
         static_assert(R == 2 * (K - 1) + 1, "row format");
@@ -337,23 +343,27 @@ struct TaggedRows {
     }
 };
 
-// Broadcast of block 0's decision: C centroids and (next pass, done).
+// Broadcast of block 0's decision: C centroids and (next pass, flag, done);
+// the flag tells, after the data-range pass, whether the two-level exchange
+// may be used.
 template <int C>
-__device__ __forceinline__ void publish_decision(SyncState* sy, uint32_t round, const float* v, int p, int done) {
+__device__ __forceinline__ void publish_decision(SyncState* sy, uint32_t round, const float* v, int p, int done,
+                                                 int flag = 0) {
 #pragma unroll
     for (int k = 0; k < C; ++k) store_tagged(sy->bcw + k, round, __builtin_bit_cast(uint32_t, v[k]));
-    store_tagged(sy->bcw + C, round, ((uint32_t)p << 1) | (uint32_t)(done != 0));
+    store_tagged(sy->bcw + C, round, ((uint32_t)p << 2) | ((uint32_t)(flag != 0) << 1) | (uint32_t)(done != 0));
 }
 
 template <int C>
 __device__ __forceinline__ bool await_decision(SyncState* sy, uint32_t round, uint64_t limit_ticks, float* v, int& p,
-                                               int& done) {
+                                               int& done, int* flag = nullptr) {
     uint32_t raw[C + 1];
     if (!poll_tagged<C + 1>(sy->bcw, round, raw, sy, wall_clock64(), limit_ticks)) return false;
 #pragma unroll
     for (int k = 0; k < C; ++k) v[k] = __builtin_bit_cast(float, raw[k]);
-    p = (int)(raw[C] >> 1);
+    p = (int)(raw[C] >> 2);
     done = (int)(raw[C] & 1u);
+    if (flag) *flag = (int)((raw[C] >> 1) & 1u);
     return true;
 }
 
@@ -796,6 +806,91 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
     return true;
 }
 
+// Two-level exchange of a persistent launch (each block's row already
+// stored to its XCD's L2).  Level 1: block x < kXcds polls the rows of blocks
+// x, x + kXcds, ... (which share its XCD; one row per thread, agent-scope
+// loads served by that L2), adds them in FP64 in that order (wave butterflies,
+// then the waves in order) and stores its XCD row with agent scope.  Level 2:
+// every block polls the (up to) kXcds XCD rows and adds them in XCD order, so
+// all blocks hold bitwise identical sums and take the decision themselves.
+// False in every thread if a wait hit its time limit.
+template <int C>
+__device__ bool xcd_exchange(const TaggedRows<2 * C + 2>& rows, int G, uint32_t round, SyncState* sy,
+                             uint64_t limit, Reduced<C>& out) {
+    constexpr int NQ = 2 * C + 1;
+    constexpr int R = partial_rows(C);
+    constexpr int XW = 2 * NQ + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint64_t* xr = &sy->xrow[round & 1u][0][0];
+    int bad = 0;
+    if ((int)blockIdx.x < kXcds) {
+        __shared__ double s_l1[kWaves][NQ];
+        __shared__ float s_l1m[kWaves];
+        const int x = blockIdx.x;
+        const int nx = (G - x + kXcds - 1) / kXcds;  // rows x, x + kXcds, ... below G
+        double acc[NQ];
+        float dm = 0.f;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+        for (int i = tid; i < nx; i += kBlock) {
+            float v[R];
+            if (!rows.template get<R>(x + kXcds * i, v)) {
+                bad = 1;
+                break;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)v[2 * q] - (double)v[2 * q + 1];
+            dm = fmaxf(dm, v[R - 1]);
+        }
+        if (__syncthreads_or(bad)) return false;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double r = wave_sum_f64(acc[q]);
+            if (lane == 0) s_l1[wid][q] = r;
+        }
+        const float m = wave_max(dm);
+        if (lane == 0) s_l1m[wid] = m;
+        __syncthreads();
+        if (tid < NQ) {
+            double r = s_l1[0][tid];
+            for (int w = 1; w < kWaves; ++w) r += s_l1[w][tid];
+            const uint64_t bits = __builtin_bit_cast(uint64_t, r);
+            store_tagged(xr + x * kXcdRowWords + 2 * tid, round, (uint32_t)bits);
+            store_tagged(xr + x * kXcdRowWords + 2 * tid + 1, round, (uint32_t)(bits >> 32));
+        } else if (tid == NQ) {
+            float mm = s_l1m[0];
+            for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_l1m[w]);
+            store_tagged(xr + x * kXcdRowWords + 2 * NQ, round, __builtin_bit_cast(uint32_t, mm));
+        }
+    }
+    __shared__ double s_l2[kXcds][NQ];
+    __shared__ float s_l2m[kXcds];
+    const int nxcd = G < kXcds ? G : kXcds;
+    if (tid < nxcd) {
+        uint32_t raw[XW];
+        if (!poll_tagged<XW>(xr + tid * kXcdRowWords, round, raw, sy, wall_clock64(), limit)) {
+            bad = 1;
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                s_l2[tid][q] = __builtin_bit_cast(double, (uint64_t)raw[2 * q] | ((uint64_t)raw[2 * q + 1] << 32));
+            s_l2m[tid] = __builtin_bit_cast(float, raw[2 * NQ]);
+        }
+    }
+    if (__syncthreads_or(bad)) return false;
+    if (tid < NQ) {
+        double r = s_l2[0][tid];
+        for (int x = 1; x < nxcd; ++x) r += s_l2[x][tid];
+        out.res[tid] = r;
+    } else if (tid == NQ) {
+        float mm = s_l2m[0];
+        for (int x = 1; x < nxcd; ++x) mm = fmaxf(mm, s_l2m[x]);
+        out.dm = mm;
+    }
+    __syncthreads();
+    return true;
+}
+
 // Outcome of pass p (Eq.3 update and Algorithm 1's test), computed identically
 // by whoever calls it.
 template <int C>
@@ -1104,8 +1199,11 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
     const bool leader = blockIdx.x == 0;
     __shared__ double s_v64[C];
     __shared__ float s_vn[C], s_vo[C];
-    __shared__ int s_p, s_done, s_ok;
-    if (tid == 0) s_ok = 1;
+    __shared__ int s_p, s_done, s_ok, s_xcd;
+    if (tid == 0) {
+        s_ok = 1;
+        s_xcd = 0;  // set after the data-range pass when the two-level exchange is usable
+    }
     __shared__ Reduced<C> s_r;
     // the last round of the previous launch (written by its block 0 before it
     // ended); tags of this launch start above it
@@ -1143,22 +1241,30 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
         }
         ++round;
         uint64_t* mm = a.mm_rows + (size_t)(round & 1u) * 2 * G;
+        // the XCD the block runs on travels with its range (two-level exchange)
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xFu;  // HW_REG_XCC_ID
         if (tid == 0) {
             // the block's counts are released before its range row
             if (learned) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            store_tagged(mm + 2 * blockIdx.x, round, lo);
+            store_tagged(mm + 2 * blockIdx.x, round, lo | (xcc << 8));
             store_tagged(mm + 2 * blockIdx.x + 1, round, hi);
         }
         if (leader || a.allgather) {
             const uint64_t t0 = wall_clock64();
+            // blocks b and b + kXcds share an XCD when the blocks were dealt
+            // to the XCDs in turn, from any starting XCD: XCD(b) - b is the
+            // same (mod kXcds) for every block, block 0's XCD here
+            int deal_bad = 0;
             auto get = [&](int b, uint32_t& l, uint32_t& h) {
                 uint32_t raw[2];
                 if (!poll_tagged<2>(mm + 2 * b, round, raw, sy, t0, a.spin_ticks)) return false;
-                l = raw[0];
+                l = raw[0] & 0xFFu;
                 h = raw[1];
+                if ((((raw[0] >> 8) - (uint32_t)b - xcc) & (kXcds - 1)) != 0u) deal_bad = 1;
                 return true;
             };
             if (!reduce_minmax(get, G, lo, hi)) return;
+            const int xcd_ok = a.xcd && leader && !__syncthreads_or(deal_bad);
             __shared__ double s_w0[kMaxC];
             if (learned) {
                 // every block whose range row was seen released its counts
@@ -1201,14 +1307,15 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 }
                 s_p = 0;
                 s_done = 0;
+                s_xcd = xcd_ok;
                 if (leader) commit_start(st, a.hist_v, C, lo, hi, v);
-                if (!a.allgather) publish_decision<C>(sy, round, s_vn, 0, 0);
+                if (!a.allgather) publish_decision<C>(sy, round, s_vn, 0, 0, xcd_ok);
             }
         } else {
             if (tid == 0) {
                 float v[C];
-                int p = 0, done = 0;
-                s_ok = await_decision<C>(sy, round, a.spin_ticks, v, p, done);
+                int p = 0, done = 0, xf = 0;
+                s_ok = await_decision<C>(sy, round, a.spin_ticks, v, p, done, &xf);
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     s_vn[k] = s_vo[k] = v[k];
@@ -1216,6 +1323,7 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 }
                 s_p = p;
                 s_done = done;
+                s_xcd = a.xcd && xf;
             }
             __syncthreads();
             if (!s_ok) return;
@@ -1256,13 +1364,18 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
         run_pass<C, MK, UNROLL>(a, p, vn, vo, acc, resident, mine);
         ++round;
         constexpr int K = 2 * C + 2;
+        const bool two_level = s_xcd != 0;
         const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * TaggedRows<K>::S * G, round, sy, (uint64_t)wall_clock64(),
-                                 a.spin_ticks};
+                                 a.spin_ticks, two_level};
         write_partial_row<C>(acc, rows);
-        if (leader || a.allgather) {
-            // every block of an all-gather launch reduces the same rows in the
-            // same order, so all hold bitwise identical results
-            if (!reduce_rows<C>(rows, G, a.kahan_only, s_r)) return;
+        if (leader || a.allgather || two_level) {
+            // every block of an all-gather or two-level launch reduces the
+            // same rows in the same order, so all hold bitwise identical results
+            if (two_level) {
+                if (!xcd_exchange<C>(rows, G, round, sy, a.spin_ticks, s_r)) return;
+            } else if (!reduce_rows<C>(rows, G, a.kahan_only, s_r)) {
+                return;
+            }
             if (tid == 0) {
                 double vcur[C];
 #pragma unroll
@@ -1270,7 +1383,7 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                 Step<C> s;
                 decide<C>(s_r, p, vcur, a.eps, a.max_iter, s);
                 if (leader) commit<C>(a, p, vcur, s);
-                if (s.done && a.labels && !a.allgather) {
+                if (s.done && a.labels && !a.allgather && !two_level) {
                     // the result in FP64 for the other blocks' label tables,
                     // tagged like the decision (which is stored after it)
 #pragma unroll
@@ -1290,7 +1403,7 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
                     s_p = p + 1;
                 }
                 s_done = s.done;
-                if (!a.allgather) publish_decision<C>(sy, round, s_vn, s_p, s.done);
+                if (!a.allgather && !two_level) publish_decision<C>(sy, round, s_vn, s_p, s.done);
             }
         } else if (tid == 0) {
             float v[C];
@@ -1314,7 +1427,7 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
             }
         }
         __syncthreads();
-        if (!leader && !a.allgather && !s_ok) return;
+        if (!leader && !a.allgather && !two_level && !s_ok) return;
     }
     if (leader && tid == 0) sy->gen = round;
     if (a.labels && s_done) {

@@ -15,13 +15,23 @@ constexpr int kMaxPersistGrid = 2048; // blocks of a cooperative launch
 // Cross-block exchange of the cooperative driver.  Zeroed when the handle is
 // created (and after an aborted solve), never by a reset: the round count only
 // grows, so tagged words of earlier rounds never match a later one.
+// Two-level exchange: the blocks are dealt to the XCDs in turn (from some
+// starting XCD), so blocks b and b + kXcds share an XCD; block x < kXcds
+// reduces the rows of blocks x, x + kXcds, ... and publishes one row of the
+// 2C + 1 FP64 sums (two tagged halves each) and the max.
+constexpr int kXcds = 8;
+constexpr int kXcdRowWords = 64;  // >= 2 (2 kMaxC + 1) + 1
+
 struct SyncState {
     uint32_t gen;             // last round of the previous cooperative launch
     uint32_t abort;           // set when a wait hit its time limit; every block then exits
-    uint64_t bcw[kMaxC + 1];  // block 0's decision: tagged centroids, then (next pass << 1 | done)
+    uint64_t bcw[kMaxC + 1];  // block 0's decision: tagged centroids, then
+                              // (next pass << 2 | two-level exchange usable << 1 | done)
     uint64_t passes_total;    // fused passes committed since the handle was created (every driver)
     uint64_t fin[2 * kMaxC];  // block 0's final centroids in FP64, two tagged halves each (fused labels)
+    alignas(128) uint64_t xrow[2][kXcds][kXcdRowWords];  // two-level exchange: XCD rows, by round parity
 };
+static_assert(2 * (2 * kMaxC + 1) + 1 <= kXcdRowWords, "XCD row too small");
 
 // Device-resident solver state.  Written only by the last block of a pass (or
 // of the data-range pass), or by block 0 of a cooperative launch; read by every
@@ -75,7 +85,7 @@ struct PassArgs {
     uint64_t* rows;        // [2][grid][16 or 32] tagged partial rows, by round parity
     uint64_t* mm_rows;     // [2][grid][2] tagged per-block grey-level range, by round parity
     int32_t allgather;     // every block reduces all rows (else block 0 reduces and broadcasts)
-    int32_t pad2;
+    int32_t xcd;           // two-level exchange through the XCDs when the dealing allows it
     int32_t do_init;       // run the data-range pass and set v^0 first
     int32_t given;         // start mode: 0 evenly spaced, 1 v0 below, 2 dv0 (device),
                            // 3 learned (persistent launch only; mlp_w, ghist below)

@@ -77,7 +77,7 @@ int validate_tuning(const fcm_tuning* t) {
         t->driver != FCM_DRIVER_HISTOGRAM)
         return FCM_EINVAL;
     if (t->graph_k < 1 || t->graph_k > kMaxGraphK) return FCM_EINVAL;
-    if (t->exchange < FCM_EXCHANGE_AUTO || t->exchange > FCM_EXCHANGE_ALLGATHER) return FCM_EINVAL;
+    if (t->exchange < FCM_EXCHANGE_AUTO || t->exchange > FCM_EXCHANGE_XCD) return FCM_EINVAL;
     if (t->launch != FCM_LAUNCH_COOPERATIVE && t->launch != FCM_LAUNCH_RESIDENT) return FCM_EINVAL;
     return FCM_OK;
 }
@@ -183,6 +183,8 @@ PassArgs pass_args(const fcm_handle* h) {
     a.allgather = (int64_t)h->grid * h->grid * (2 * h->p.n_clusters + 2) * 8 <= kAllGatherBytes ? 1 : 0;
     if (h->tun.exchange == FCM_EXCHANGE_LEADER) a.allgather = 0;
     if (h->tun.exchange == FCM_EXCHANGE_ALLGATHER) a.allgather = 1;
+    a.xcd = h->tun.exchange == FCM_EXCHANGE_XCD ? 1 : 0;
+    if (a.xcd) a.allgather = 0;  // the data-range round and any fallback use the leader
     a.do_init = h->pending_init ? 1 : 0;
     a.given = start_mode(h->p.init);
     for (int k = 0; k < kMaxC; ++k) a.v0[k] = h->given[k];
@@ -600,6 +602,7 @@ int fcm_set_tuning(fcm_handle* h, const fcm_tuning* t) {
     if (!pass_supported(h->p.n_clusters, h->mclass, t->unroll)) return FCM_EUNSUPPORTED;
     if (t->driver == FCM_DRIVER_PERSISTENT && !h->coop) return FCM_EUNSUPPORTED;
     if (t->driver == FCM_DRIVER_HISTOGRAM && h->p.init == FCM_INIT_RANDOM_U) return FCM_EINVAL;
+    if (t->exchange == FCM_EXCHANGE_XCD && (h->p.flags & FCM_F_KAHAN_ONLY)) return FCM_EUNSUPPORTED;
     const fcm_tuning old = h->tun;
     h->tun = *t;
     int grid = 1;

@@ -203,8 +203,9 @@ int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning
     for (int unroll : {1, 2}) {
         if (s.coop) {
             for (int g : grids) {
-                for (int ex : {FCM_EXCHANGE_LEADER, FCM_EXCHANGE_ALLGATHER}) {
+                for (int ex : {FCM_EXCHANGE_LEADER, FCM_EXCHANGE_ALLGATHER, FCM_EXCHANGE_XCD}) {
                     if (ex == FCM_EXCHANGE_ALLGATHER && g > kMaxAllGatherGrid) continue;
+                    if (ex == FCM_EXCHANGE_XCD && s.kahan) continue;
                     fcm_tuning t = entry;
                     t.driver = FCM_DRIVER_PERSISTENT;
                     t.grid = g;

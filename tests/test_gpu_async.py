@@ -96,7 +96,7 @@ def test_async_many_sizes(torch_dev):
             same(r, ref)
 
 
-@pytest.mark.parametrize("exchange", [1, 2])
+@pytest.mark.parametrize("exchange", [1, 2, 3])
 @pytest.mark.parametrize("grid", [0, 8])
 @pytest.mark.parametrize("x_off,lab_off", [(0, 0), (5, 5), (0, 3), (7, 1)])
 def test_fused_labels(torch_dev, exchange, grid, x_off, lab_off):

@@ -94,7 +94,7 @@ def test_ragged_sizes_and_offsets(torch_dev, n, offset):
     check_against_literal(torch_dev, x, 4)
 
 
-@pytest.mark.parametrize("driver,exchange", [(0, 0), (2, 1), (2, 2)])
+@pytest.mark.parametrize("driver,exchange", [(0, 0), (2, 1), (2, 2), (2, 3)])
 @pytest.mark.parametrize("grid,unroll", [(1, 1), (3, 2), (77, 1), (256, 2), (1024, 1), (4096, 2)])
 def test_launch_shapes(torch_dev, grid, unroll, driver, exchange):
     announce("launch grid", grid, "unroll", unroll, "driver", driver, "exchange", exchange)
@@ -104,12 +104,43 @@ def test_launch_shapes(torch_dev, grid, unroll, driver, exchange):
 
 @pytest.mark.parametrize("driver,k,exchange,launch", [(0, 1, 0, 0), (0, 5, 0, 0), (1, 1, 0, 0), (1, 3, 0, 0),
                                                       (1, 16, 0, 0), (2, 1, 0, 0), (2, 1, 1, 0), (2, 1, 2, 0),
-                                                      (2, 1, 0, 1), (2, 1, 1, 1), (2, 1, 2, 1)])
+                                                      (2, 1, 0, 1), (2, 1, 1, 1), (2, 1, 2, 1), (2, 1, 3, 0),
+                                                      (2, 1, 3, 1), (2, 3, 3, 1)])
 @pytest.mark.parametrize("shape", [(200, 200), (32, 160, 160)])
 def test_drivers(torch_dev, driver, k, exchange, launch, shape):
     announce("driver", driver, "graph_k", k, "exchange", exchange, "launch", launch, "shape", shape)
     x = phantom(PhantomParams(shape=shape, seed=1))
     check_against_literal(torch_dev, x, 4, tuning=dict(driver=driver, graph_k=k, exchange=exchange, launch=launch))
+
+
+@pytest.mark.parametrize("C,m", [(2, 2.0), (5, 1.5), (8, 2.5), (7, 3.0)])
+def test_two_level_exchange_clusters(torch_dev, C, m):
+    """The exchange through the XCDs across cluster counts and fuzziness (FP64
+    sums in another fixed order than the one-level exchanges)."""
+    announce("two-level exchange C", C, "m", m)
+    x = phantom(PhantomParams(shape=(48, 128, 128), seed=10 + C))
+    check_against_literal(torch_dev, x, C, m=m, tuning=dict(driver=2, exchange=3))
+
+
+def test_two_level_exchange_after_odd_dispatches(torch_dev):
+    """Launches of 1..9 blocks in between move the XCD the next launch starts
+    on; the two-level solves (or their fallback) still match the oracle."""
+    torch, dev = torch_dev
+    from paper_1601_00072_amd import FCM
+    announce("two-level exchange after odd dispatches")
+    x = phantom_2d(200, 200, seed=1)
+    ref = fcm_ref.solve(x, 4, 2.0, 1e-5, 300)
+    xt = torch.from_numpy(x.ravel()).to(dev)
+    for blocks in range(1, 10):
+        y = torch.from_numpy(np.arange(blocks * 4096, dtype=np.int64) % 251).to(dev).to(torch.uint8)
+        with FCM(y, 3) as g:
+            g.set_tuning(driver=2, grid=blocks, exchange=1)
+            g.solve()
+        with FCM(xt, 4) as f:
+            f.set_tuning(driver=2, exchange=3)
+            r = f.solve()
+        assert r.iters == ref.T
+        assert np.max(np.abs(r.centroids - ref.v[ref.T]) / np.maximum(np.abs(ref.v[ref.T]), 1.0)) <= 1e-5
 
 
 # --- cluster counts and fuzziness -------------------------------------------
