@@ -256,7 +256,7 @@ void fcm_batch_destroy(fcm_batch* b);
  * during the call. */
 
 /* Single instance: persistent driver (ordinary launch) over grids from half
- * the CU count up to one 16-voxel chunk per thread, leader and all-gather
+ * the CU count up to one 16-voxel chunk per thread, leader, all-gather and two-level
  * exchange, unroll 1 and 2; graph driver with 4 and 16 passes per graph.
  * Key: C, the m class (2, 1.5, other), the precision flag and floor(log2 n).
  * The handle is left reset with the chosen tuning (chosen may be NULL; ms:
