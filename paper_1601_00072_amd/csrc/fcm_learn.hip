@@ -99,60 +99,53 @@ hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int coun
 // ---------------------------------------------------------------------------
 // FP32 GEMM for training: Cm[M][N] = op(A) op(B) (+ bias[N]) (ReLU) (* mask>0)
 // op(A) is A [M][K] or, transposed, A [K][M]; op(B) is B [K][N] or B [N][K].
-// 32 x 32 output tile per block of 16 x 16 threads (2 x 2 outputs each), K in
-// steps of 32 through LDS.  Each output is a sum in a fixed order.
+// The training shapes are small (K and M up to 256 rows of a minibatch), so
+// the output is cut into 16 x 16 tiles, one output per thread (enough blocks
+// to spread over the chip), K in steps of 16 through LDS.  Each output is a
+// sum over k in increasing order.
 // ---------------------------------------------------------------------------
 
-constexpr int kT = 32;
+constexpr int kT = 16;  // 16 x 16 outputs per block, one per thread; K in steps of 16
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_kernel(const float* A, const float* B, float* Cm, int M, int N, int K,
                                                    const float* bias, int relu, const float* mask) {
-    __shared__ float As[kT][kT + 1];
-    __shared__ float Bs[kT][kT + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    __shared__ float As[kT][kT + 1];  // [m][k]
+    __shared__ float Bs[kT][kT + 1];  // [k][n]
+    const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
     const int row0 = blockIdx.y * kT, col0 = blockIdx.x * kT;
-    float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    float acc = 0.f;
     for (int k0 = 0; k0 < K; k0 += kT) {
-        // consecutive threads take consecutive addresses of the stored
-        // layout (transposed operands walk the tile the other way round)
-        for (int e = threadIdx.x; e < kT * kT; e += 256) {
-            const int r = TA ? e % kT : e / kT, c = TA ? e / kT : e % kT;  // As[m][k]
+        // one element of each tile per thread; consecutive threads take
+        // consecutive addresses of the stored layout (transposed operands
+        // walk the tile the other way round)
+        const int e = threadIdx.x;
+        {
+            const int r = TA ? e % kT : e / kT, c = TA ? e / kT : e % kT;
             const int gm = row0 + r, gk = k0 + c;
             float va = 0.f;
             if (gm < M && gk < K) va = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
             As[r][c] = va;
-            const int rb = TB ? e % kT : e / kT, cb = TB ? e / kT : e % kT;  // Bs[k][n]
-            const int gk2 = k0 + rb, gn = col0 + cb;
+        }
+        {
+            const int rb = TB ? e % kT : e / kT, cb = TB ? e / kT : e % kT;
+            const int gk = k0 + rb, gn = col0 + cb;
             float vb = 0.f;
-            if (gk2 < K && gn < N) vb = TB ? B[(int64_t)gn * K + gk2] : B[(int64_t)gk2 * N + gn];
+            if (gk < K && gn < N) vb = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
             Bs[rb][cb] = vb;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < kT; ++kk) {
-            const float a0 = As[ty * 2][kk], a1 = As[ty * 2 + 1][kk];
-            const float b0 = Bs[kk][tx * 2], b1 = Bs[kk][tx * 2 + 1];
-            acc[0][0] = fmaf(a0, b0, acc[0][0]);
-            acc[0][1] = fmaf(a0, b1, acc[0][1]);
-            acc[1][0] = fmaf(a1, b0, acc[1][0]);
-            acc[1][1] = fmaf(a1, b1, acc[1][1]);
-        }
+#pragma unroll
+        for (int kk = 0; kk < kT; ++kk) acc = fmaf(As[ty][kk], Bs[kk][tx], acc);
         __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int gm = row0 + ty * 2 + i, gn = col0 + tx * 2 + j;
-            if (gm >= M || gn >= N) continue;
-            float v = acc[i][j];
-            if (bias) v += bias[gn];
-            if (relu) v = fmaxf(v, 0.f);
-            if (mask && !(mask[(int64_t)gm * N + gn] > 0.f)) v = 0.f;
-            Cm[(int64_t)gm * N + gn] = v;
-        }
-    }
+    const int gm = row0 + ty, gn = col0 + tx;
+    if (gm >= M || gn >= N) return;
+    float v = acc;
+    if (bias) v += bias[gn];
+    if (relu) v = fmaxf(v, 0.f);
+    if (mask && !(mask[(int64_t)gm * N + gn] > 0.f)) v = 0.f;
+    Cm[(int64_t)gm * N + gn] = v;
 }
 
 hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* Cm, int M, int N, int K,
