@@ -302,8 +302,9 @@ def test_trained_network_gain(torch_dev):
     assert ev["max_rel_J_excess_accepted"] <= 1e-6
 
 
-@pytest.mark.parametrize("shape,driver", [((64, 128, 128), 2), ((64, 128, 128), 1), ((173, 211), 2)])
-def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver):
+@pytest.mark.parametrize("shape,driver,exchange", [((64, 128, 128), 2, 0), ((64, 128, 128), 1, 0), ((173, 211), 2, 0),
+                                                    ((64, 128, 128), 2, 3), ((173, 211), 2, 3)])
+def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver, exchange):
     """The persistent driver computes the histogram and runs the network inside
     its one launch; the graph driver launches the histogram and network
     kernels first.  Both must start from the start the oracle derives (FP64
@@ -311,7 +312,7 @@ def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver):
     torch, d = torch_dev
     from paper_1601_00072_amd import FCM, MLP
     from tests import _parity as P
-    announce("warm start", shape, "driver", driver)
+    announce("warm start", shape, "driver", driver, "exchange", exchange)
     x = phantom(PhantomParams(shape=shape, seed=17)).ravel()
     xt = torch.from_numpy(x).to(d)
     h = fcm_hist.histogram(x)
@@ -320,7 +321,7 @@ def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver):
         theta = net.params().astype(np.float64)
         y = mlp_ref.forward_bf16(theta, hn[None, :], 4)[0]
         with FCM(xt, 4) as f:
-            f.set_tuning(driver=driver)
+            f.set_tuning(driver=driver, exchange=exchange)
             res, used, _ = f.solve_warm(net, check=False)
             traj = P.gpu_trajectory(f, res.iters)
             lab = f.labels().cpu().numpy()
