@@ -93,7 +93,11 @@ extern "C" {
                                      block adds the 8 XCD rows itself (no broadcast).  The
                                      dealing is checked in the data-range pass of each solve;
                                      where it differs, and for launches that continue a solve,
-                                     the leader exchange is used.  Not with FCM_F_KAHAN_ONLY */
+                                     the leader exchange is used.  The in-XCD step relies on the
+                                     XCD's L2 making a workgroup-scope store visible to an
+                                     agent-scope load of another block on that XCD (measured on
+                                     MI355X); where it did not, a wait would end at its time
+                                     limit with FCM_EDEVICE.  Not with FCM_F_KAHAN_ONLY */
 
 /* how the persistent driver launches its kernel */
 #define FCM_LAUNCH_COOPERATIVE 0  /* hipLaunchCooperativeKernel: the runtime guarantees
