@@ -384,6 +384,9 @@ def batched(dev, tune_cache):
         torch.cuda.synchronize()
         el_b = (time.perf_counter() - t0) / reps
     vox_passes = sum(a.size * r.passes for a, r in zip(xs, res))
+    # algorithmic lane-ops of every instance (its own C and pass count)
+    ops = sum(a.size * (alg_lane_ops(c, 2.0, False) + (r.passes - 1) * alg_lane_ops(c, 2.0, True))
+              for a, c, r in zip(xs, Cs, res))
     # per-instance launch loop: the single-instance solver, one instance after another
     views, off = [], 0
     for a in xs:
@@ -406,6 +409,7 @@ def batched(dev, tune_cache):
             "voxels": n, "max_iterations": max(r.iters for r in res),
             "ms_per_batch_solve": el_b * 1e3, "voxel_iterations_per_s": vox_passes / el_b,
             "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b,
+            "roofline_frac_wall": ops / el_b / PEAK_LANE_OPS,
             "tiling": {"chunks_per_thread": cpt, "grid": bgrid}}
 
 
