@@ -83,3 +83,76 @@ def test_forward_bf16_reduces_to_forward_on_representable_values():
     X[0, 0] = 0.375
     X[1, 0] = 0.75
     assert np.array_equal(mlp_ref.forward_bf16(theta, X, C), mlp_ref.forward(theta, X, C)[0])
+
+
+def _hand_network():
+    """A network with a handful of nonzero parameters whose outputs are worked
+    out by hand below: nonzero hidden biases, one negative pre-activation in
+    each hidden layer for one of the two samples, and a unit fed only by its
+    bias.  Every value is a short dyadic fraction, exact in FP64 and in BF16."""
+    C = 2
+    theta = np.zeros(mlp_ref.n_params(C))
+    W1, b1, W2, b2, W3, b3 = mlp_ref.unpack(theta, C)
+    # layer 1: z1_0 = x0 + 2 x1 + 1/2, z1_1 = -3 x0 + 1, z1_2 = 4 x1 - 1,
+    # z1_3 = -1/4 (always cut by the ReLU), z1_4 = 3/4 (bias only)
+    W1[0, 0], W1[1, 0], b1[0] = 1.0, 2.0, 0.5
+    W1[0, 1], b1[1] = -3.0, 1.0
+    W1[1, 2], b1[2] = 4.0, -1.0
+    b1[3] = -0.25
+    b1[4] = 0.75
+    # layer 2: z2_0 = h0 - 2 h1 + h2/2 + h4 + 1/4, z2_1 = -h0 + 2 h2 - 1/2
+    W2[0, 0], W2[1, 0], W2[2, 0], W2[4, 0], b2[0] = 1.0, -2.0, 0.5, 1.0, 0.25
+    W2[0, 1], W2[2, 1], b2[1] = -1.0, 2.0, -0.5
+    # output: y0 = 2 g0 + g1 - 1, y1 = -g0 + 4 g1 + 1/2
+    W3[0, 0], W3[1, 0], b3[0] = 2.0, 1.0, -1.0
+    W3[0, 1], W3[1, 1], b3[1] = -1.0, 4.0, 0.5
+    X = np.zeros((2, 256))
+    X[0, :2] = [0.5, 0.25]
+    X[1, :2] = [0.125, 0.75]
+    return theta, X, C
+
+
+def test_forward_fixed_values_worked_by_hand():
+    """Sample A (x0 = 1/2, x1 = 1/4):
+      z1 = (3/2, -1/2, 0, -1/4, 3/4) -> h1 = (3/2, 0, 0, 0, 3/4)   (z1_1 < 0 cut)
+      z2 = (3/2 + 3/4 + 1/4, -3/2 - 1/2) = (5/2, -2) -> h2 = (5/2, 0)   (z2_1 < 0 cut)
+      y  = (5 - 1, -5/2 + 1/2) = (4, -2)                              (no ReLU on y)
+    Sample B (x0 = 1/8, x1 = 3/4):
+      z1 = (17/8, 5/8, 2, -1/4, 3/4) -> h1 = (17/8, 5/8, 2, 0, 3/4)
+      z2 = (17/8 - 5/4 + 1 + 3/4 + 1/4, -17/8 + 4 - 1/2) = (23/8, 11/8)
+      y  = (23/4 + 11/8 - 1, -23/8 + 11/2 + 1/2) = (49/8, 25/8)
+    A dropped hidden bias, a ReLU missing from either hidden layer, a ReLU on
+    the output or a transposed layer each change at least one of these."""
+    theta, X, C = _hand_network()
+    y, (_, z1, h1, z2, h2) = mlp_ref.forward(theta, X, C)
+    assert z1[0, :5].tolist() == [1.5, -0.5, 0.0, -0.25, 0.75]
+    assert h1[1, :5].tolist() == [2.125, 0.625, 2.0, 0.0, 0.75]
+    assert z2[:, :2].tolist() == [[2.5, -2.0], [2.875, 1.375]]
+    assert h2[0, :2].tolist() == [2.5, 0.0]
+    assert y.tolist() == [[4.0, -2.0], [6.125, 3.125]]
+    # every value above is a BF16 value, so the BF16 forward is exact too
+    assert mlp_ref.forward_bf16(theta, X, C).tolist() == [[4.0, -2.0], [6.125, 3.125]]
+
+
+def test_gradient_fixed_values_worked_by_hand():
+    """The chain rule on the hand network with targets t = y - (1, 0) for
+    sample A and t = y for sample B: dL/dy = 2 (y - t) / (B C) = (1/2, 0) on
+    sample A only.  Then dL/db3 = (1/2, 0), dL/dW3[0,0] = g0(A)/2 = 5/4,
+    dL/dW3[1,0] = g1(A)/2 = 0, and back through the active units of sample A:
+    dL/dz2_0 = 2 * 1/2 = 1 (z2_1 was cut), dL/db2 = (1, 0),
+    dL/dW2[0,0] = h0 = 3/2, dL/dW2[4,0] = h4 = 3/4, dL/dW2[1,0] = h1 = 0;
+    dL/dz1 = W2[:, 0] masked by z1 > 0 = (1, 0, 0, 0, 1), so
+    dL/db1[:5] = (1, 0, 0, 0, 1), dL/dW1[0,0] = x0 = 1/2, dL/dW1[1,0] = 1/4."""
+    theta, X, C = _hand_network()
+    y, _ = mlp_ref.forward(theta, X, C)
+    T = y.copy()
+    T[0, 0] -= 1.0
+    g = mlp_ref.unpack(mlp_ref.grad(theta, X, T, C), C)
+    gW1, gb1, gW2, gb2, gW3, gb3 = g
+    assert gb3.tolist() == [0.5, 0.0]
+    assert gW3[:2].tolist() == [[1.25, 0.0], [0.0, 0.0]]
+    assert gb2[:2].tolist() == [1.0, 0.0]
+    assert [gW2[0, 0], gW2[1, 0], gW2[4, 0], gW2[2, 0]] == [1.5, 0.0, 0.75, 0.0]
+    assert gb1[:5].tolist() == [1.0, 0.0, 0.0, 0.0, 1.0]
+    assert [gW1[0, 0], gW1[1, 0], gW1[0, 4]] == [0.5, 0.25, 0.5]
+    assert np.count_nonzero(gW1) == 4      # W1[0,0], W1[1,0], W1[0,4], W1[1,4]
