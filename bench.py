@@ -2,18 +2,22 @@
 
 A step is one whole solve on a resident input: the data-range pass and v^0,
 fused passes until max |dU| < eps, and the defuzzified labels.  Headline
-workload: the 128x128x64 (1,048,576-voxel) ellipsoid-shell phantom, seed 2,
-sigma 8, bias 10 %, C = 4, m = 2, eps = 1e-5, max 300 iterations.
+workload: the largest single-GPU volume, the 512x512x256 (67,108,864-voxel)
+ellipsoid-shell phantom, seed 3, noise sigma 9, bias 20 %, C = 4, m = 2,
+eps = 1e-5, max 300 iterations.
 
 Prints one JSON line.  ``value`` = voxel-iterations/s = n * passes / wall time
-of the timed steps (passes = T + 1 per solve).  ``roofline`` refers to the
-dominant kernel, the persistent solve kernel (one launch per solve runs the
-data-range pass and every fused pass): algorithmic VALU lane-ops per voxel and
-pass (``alg_lane_ops``) times the voxels and passes of a launch, over the
-launch's average duration from HIP events recorded on the solve's stream.
+of the timed steps (passes = T + 1 per solve, counted on the device).
+``roofline`` refers to the dominant kernel, the persistent solve kernel (one
+launch per solve runs the data-range pass and every fused pass): achieved
+voxel-passes per second of launch time (HIP events on the solve's stream)
+against the ALU roofline of a fixed count of lane-ops per voxel-iteration
+(``fixed_ops``), with the library's own op count beside it.
 ``cpu_baseline`` is the FP64 oracle timed on the host on the same volume.
-``extra`` holds two further measured workloads (the 512x512x256 volume and the
-512-instance batch against a per-instance loop); ``--quick`` skips them.
+``extra`` holds the other measured workloads (the 128x128x64 volume, the
+200x200 slice and the per-pass latency floor, the 512-instance batch, the
+learned warm start, the histogram-domain driver, Dice, the paper's protocol
+and the paper's GPU design); ``--quick`` skips them.
 """
 from __future__ import annotations
 
@@ -26,22 +30,50 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; one FP32 VALU op per lane per
-# cycle without packed FP32, transcendental ops (rcp, exp2, log2, sqrt) at
-# quarter rate, i.e. 4 lane-op slots each.
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # 3.93e13 lane-op/s
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  Rates of the fixed count:
+# packed FP32 add/mul/fma 7.86e13 lane-op/s (157.3 TFLOP/s / 2), unpacked ops
+# (max, compare) 3.93e13, transcendentals (rcp, sqrt, exp2, log2) at quarter
+# rate 9.83e12.
+RATE_PACKED = 256 * 4 * 16 * 2.4e9 * 2
+RATE_UNPACKED = 256 * 4 * 16 * 2.4e9
+RATE_TRANS = RATE_UNPACKED / 4
+PEAK_LANE_OPS = RATE_UNPACKED  # one FP32 VALU op per lane per cycle (this build: no packed FP32)
 HBM_PEAK = 8.0e12
 METRIC = "FCM voxel-iterations/s & time-to-converge (eps=1e-5) vs plain init, % roofline"
 
 
-def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
-    """Algorithmic VALU lane-op slots per voxel for one fused pass.
+def fixed_ops(C: int, m: float):
+    """Lane-ops per voxel-iteration fixed in advance from the method (not from
+    the kernel): (packable add/mul/fma, unpacked, transcendental).
+    One membership evaluation (Eq.4): m = 2: 4C - 1 add/mul and C + 1
+    transcendentals; m = 1.5: 5C - 1 and C + 1; other m: 5C - 1 and 2C + 1.
+    A pass evaluates the new and the previous memberships (two evaluations),
+    then u^m (m = 2: C mul; 1.5: C sqrt + C mul; other: C sqrt + 2C mul),
+    the Eq.3/Eq.1 accumulations (3C) and the change test (C sub, C max)."""
+    if m == 2.0:
+        ev, tr, um, umt = 4 * C - 1, C + 1, C, 0
+    elif m == 1.5:
+        ev, tr, um, umt = 5 * C - 1, C + 1, C, C
+    else:
+        ev, tr, um, umt = 5 * C - 1, 2 * C + 1, 2 * C, C
+    return 2 * ev + um + 3 * C + C, C, 2 * tr + umt
 
-    Counts the arithmetic of Eq.1, Eq.3, Eq.4 and the stopping test in the
-    cheapest membership form known to this library, with the fused forms the
-    ISA offers (fma where a product feeds a sum, max3 for running maxima) and
-    transcendentals weighted 4.  Excludes byte-to-float conversion, Kahan
-    compensation, range/separation tests and all reductions.
+
+def alu_ceiling(C: int, m: float) -> float:
+    """Voxel-iterations/s at the ALU roofline of the fixed count (each class
+    at its own rate, one shared issue)."""
+    p, u, t = fixed_ops(C, m)
+    return 1.0 / (p / RATE_PACKED + u / RATE_UNPACKED + t / RATE_TRANS)
+
+
+def alg_lane_ops(C: int, m: float, with_old: bool = True) -> float:
+    """The library's own count of VALU lane-op slots per voxel for one fused
+    pass (the membership forms it uses; reported beside the fixed count).
+
+    Counts the arithmetic of Eq.1, Eq.3, Eq.4 and the stopping test with the
+    fused forms the ISA offers (fma where a product feeds a sum, max3 for
+    running maxima) and transcendentals weighted 4.  Excludes byte-to-float
+    conversion, Kahan compensation, range/separation tests and all reductions.
       m = 2, one evaluation (product form):
         C sub + C mul (q) + (3C - 6) mul (leave-one-out products)
         + (C - 1) add (sum) + 4 (rcp) + C mul (scale)          = 7C - 3
@@ -70,8 +102,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--shape", default="64,128,128", help="D,H,W (or H,W) of the phantom")
-    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--shape", default="256,512,512", help="D,H,W (or H,W) of the phantom")
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--sigma", type=float, default=9.0, help="noise sigma of the phantom")
+    ap.add_argument("--bias", type=float, default=0.2, help="bias-field amplitude of the phantom")
     ap.add_argument("--clusters", type=int, default=4)
     ap.add_argument("--m", type=float, default=2.0)
     ap.add_argument("--eps", type=float, default=1e-5)
@@ -91,30 +125,40 @@ def parse():
 def cpu_baseline(x_np, C, m, eps, budget_s):
     """The oracle on the same volume.  Oracle-F (plain C, FP64, one static
     chunk of voxels per thread) on the host's cores -- at most 16, the CPU
-    share of one GPU -- runs the whole solve; the literal numpy oracle on one
-    core runs passes until converged or until the time budget is spent.
-    Both in voxel-iterations/s; the threaded figure is the baseline."""
+    share of one GPU -- runs the whole solve over every voxel; the literal
+    numpy oracle on one core runs on a bounded sample (at most 2^20 voxels
+    from the middle of the volume) until converged or until the time budget
+    is spent.  Both in voxel-iterations/s; the threaded figure is the
+    baseline."""
     import numpy as np
 
     from oracle import fcm_fast, fcm_ref
     x = x_np.ravel()
     n = x.size
-    threads = max(1, min(16, os.cpu_count() or 1))
+    host = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = host
+    threads = max(1, min(16, avail))
     fcm_fast.solve(x[:4096], C, m=m, eps=eps, threads=threads)  # load the library
     t0 = time.perf_counter()
     tr = fcm_fast.solve(x, C, m=m, eps=eps, max_iter=300, threads=threads)
     el_f = time.perf_counter() - t0
     passes_f = tr.T + 1
-    # literal oracle, one core
+    # literal oracle, one core, on a bounded sample of the same volume
+    ns = min(n, 1 << 20)
+    s0 = (n - ns) // 2
+    xs = x[s0:s0 + ns]
     t0 = time.perf_counter()
-    v = fcm_ref.linspace_init(int(x.min()), int(x.max()), C)
-    U = fcm_ref.memberships(x, v, m)
+    v = fcm_ref.linspace_init(int(xs.min()), int(xs.max()), C)
+    U = fcm_ref.memberships(xs, v, m)
     passes = 1
     t = 0
     while True:
         t += 1
-        v = fcm_ref.centroids(x, U, m, v)
-        U_new = fcm_ref.memberships(x, v, m)
+        v = fcm_ref.centroids(xs, U, m, v)
+        U_new = fcm_ref.memberships(xs, v, m)
         delta = float(np.max(np.abs(U_new - U)))
         U = U_new
         passes += 1
@@ -122,12 +166,14 @@ def cpu_baseline(x_np, C, m, eps, budget_s):
             break
     el = time.perf_counter() - t0
     return {"value": n * passes_f / el_f, "unit": "voxel-iterations/s", "cores": threads, "kind": "oracle",
+            "host_cpu_count": host, "cpus_available": avail,
             "sample": f"the whole solve ({tr.T} iterations, {passes_f} membership sweeps) of the FP64 C oracle "
-                      f"(Oracle-F, per voxel, {threads} threads) over all {n} voxels of the same volume: "
-                      f"{el_f:.3f} s",
-            "literal_single_core": {"value": n * passes / el, "unit": "voxel-iterations/s", "cores": 1,
-                                    "sample": f"the whole solve ({t} iterations, {passes} membership evaluations) "
-                                              f"of the FP64 literal numpy oracle over all {n} voxels: {el:.2f} s"}}
+                      f"(Oracle-F, per voxel, {threads} threads of {avail} available, {host} on the host) over all "
+                      f"{n} voxels of the same volume: {el_f:.3f} s",
+            "literal_single_core": {"value": ns * passes / el, "unit": "voxel-iterations/s", "cores": 1,
+                                    "sample": f"{t} iterations ({passes} membership evaluations) of the FP64 "
+                                              f"literal numpy oracle over voxels {s0}..{s0 + ns - 1} of the same "
+                                              f"volume: {el:.2f} s"}}
 
 
 def timed_solves(f, steps, labels=None):
@@ -163,7 +209,7 @@ def timed_async(f, steps, labels):
     return time.perf_counter() - t0, tot - tot0, r.kernel_ms, r
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fcm_persist_kernel_volume_1M_c4_m2.md")
+PROFILES = os.path.join(ROOT, "profiles")
 TUNE_CACHE = os.path.join(ROOT, "paper_1601_00072_amd", "tuning_mi355x.txt")
 
 
@@ -204,67 +250,154 @@ def tuning_tag(t) -> str:
     return f"grid={t['grid']},unroll={t['unroll']},exchange={t['exchange']},launch={t['launch']}"
 
 
-def recorded_traffic(shape, C, m, tuning):
-    """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary, or None when it was taken on other device sources, another
-    workload or another launch configuration."""
-    try:
-        with open(TRAFFIC_PROFILE) as fh:
-            for line in fh:
-                f = line.split()
-                if f[:1] == ["traffic_bytes_per_launch:"]:
-                    kv = dict(zip(f[0::2], f[1::2]))
-                    same = (kv.get("sources_digest:") == sources_digest(C)
-                            and kv.get("tuning:") == tuning_tag(tuning)
-                            and kv.get("workload:") == ",".join(map(str, shape))
-                            and f"C={C}" in f and f"m={float(m)}" in f)
-                    return int(kv["traffic_bytes_per_launch:"]) if same else None
-    except OSError:
-        return None
+def recorded(key, shape, C, m, tuning):
+    """A machine-readable line `key: value ... sources_digest: D tuning: T
+    workload: W C=.. m=..` from the committed profile summaries, as a dict of
+    its fields, or None when none was taken on the current kernel sources,
+    this workload and this launch configuration."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        try:
+            with open(path) as fh:
+                lines = fh.readlines()
+        except OSError:
+            continue
+        for line in lines:
+            f = line.split()
+            if f[:1] != [key + ":"]:
+                continue
+            kv = dict(zip(f[0::2], f[1::2]))
+            if (kv.get("sources_digest:") == sources_digest(C) and kv.get("tuning:") == tuning_tag(tuning)
+                    and kv.get("workload:") == ",".join(map(str, shape)) and f"C={C}" in f and f"m={float(m)}" in f):
+                return {k.rstrip(":"): v for k, v in kv.items()}
     return None
 
 
+def recorded_traffic(shape, C, m, tuning):
+    """HBM bytes per launch of the persistent kernel (copy-calibrated
+    FETCH_SIZE + WRITE_SIZE) from the committed summaries, or None."""
+    kv = recorded("traffic_bytes_per_launch", shape, C, m, tuning)
+    return None if kv is None else int(kv["traffic_bytes_per_launch"])
+
+
+def recorded_counters(shape, C, m, tuning):
+    """VALU counters of the persistent kernel per voxel-pass from the
+    committed summaries (rocprofv3 --pmc), or None."""
+    kv = recorded("valu_counters", shape, C, m, tuning)
+    if kv is None:
+        return None
+    out = {}
+    for k, v in kv.items():
+        if k in ("valu_counters", "sources_digest", "tuning", "workload"):
+            continue
+        try:
+            out[k] = float(v)
+        except ValueError:
+            out[k] = v
+    return out
+
+
 def roofline(n, C, m, passes_per_launch, launch_s):
+    """Achieved rates of one launch: voxel-passes per second, and the
+    library's own lane-op count per second (the first pass evaluates one
+    membership set, the others two)."""
+    vox = n * passes_per_launch / launch_s
     ops = n * (alg_lane_ops(C, m, False) + (passes_per_launch - 1) * alg_lane_ops(C, m, True))
-    achieved = ops / launch_s
-    return achieved
+    return vox, ops / launch_s
 
 
-def large_volume(dev, tune_cache):
+def roofline_entry(shape, n, C, m, passes_per_launch, launch_s, tuning, kernel):
+    vox, ops = roofline(n, C, m, passes_per_launch, launch_s)
+    ceil = alu_ceiling(C, m)
+    p, u, t = fixed_ops(C, m)
+    return {
+        "bound": "alu",
+        "kernel": kernel,
+        "achieved": vox,
+        "peak": ceil,
+        "unit": "voxel-iterations/s",
+        "frac": vox / ceil,
+        "traffic": recorded_traffic(shape, C, m, tuning),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "launch_avg_us": launch_s * 1e6,
+        "passes_per_launch": passes_per_launch,
+        "peak_basis": f"fixed count per voxel-iteration: {p} packable add/mul/fma, {u} unpacked, {t} "
+                      f"transcendental lane-ops at {RATE_PACKED:.3g} / {RATE_UNPACKED:.3g} / {RATE_TRANS:.3g} "
+                      f"per s (256 CUs x 4 SIMD x 16 lanes, 2.4 GHz)",
+        "library_count": {"lane_ops_per_voxel_pass": alg_lane_ops(C, m, True), "achieved_T_lane_op_s": ops / 1e12,
+                          "peak_T_lane_op_s": PEAK_LANE_OPS / 1e12, "frac": ops / PEAK_LANE_OPS},
+        "hbm": {"algorithmic_GB_s": vox / 1e9, "frac_of_8TB_s": vox / HBM_PEAK},
+        "counters": recorded_counters(shape, C, m, tuning),
+    }
+
+
+def solve_steps(dev, x, C, m, eps, steps, warmup, launch, autotune, tune_cache):
+    """The timed steps on one resident input: `warmup` + `steps` whole solves
+    with labels enqueued back to back (fcm_solve_async), then the same solves
+    waited for one at a time (fcm_solve + fcm_labels)."""
     import torch
 
     from paper_1601_00072_amd import FCM
-    from phantom import PhantomParams, phantom
-    shape = (256, 512, 512)
-    x = torch.from_numpy(phantom(PhantomParams(shape=shape, seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
-    n = x.numel()
-    f = FCM(x, 4, timing=True)
-    f.autotune(cache=tune_cache, reps=2)
-    timed_solves(f, 1)
-    el, passes, kms, r = timed_solves(f, 3)
-    tun = f.tuning
+    labels = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    f = FCM(x, C, m=m, eps=eps, max_iter=300, timing=True, stream=stream)
+    f.set_tuning(launch=0 if launch == "cooperative" else 1)
+    if autotune:
+        f.autotune(cache=tune_cache, reps=3)
+    timed_async(f, warmup, labels)
+    tuning = f.tuning
+    el, passes_total, kernel_ms_total, r = timed_async(f, steps, labels)
+    el_sync, passes_sync, _, _ = timed_solves(f, steps, labels)
     f.close()
-    launch_s = kms / 3 * 1e-3
-    ach = roofline(n, 4, 2.0, r.passes, launch_s)
-    return {"workload": "ellipsoid-shell phantom 512x512x256 (67,108,864 voxels), seed 3, sigma 9, bias 20%, "
-                        "C=4, m=2, eps=1e-5",
-            "iterations": r.iters, "ms_per_solve": el / 3 * 1e3, "voxel_iterations_per_s": n * passes / el,
-            "us_per_pass": launch_s / r.passes * 1e6, "tuning": tun,
-            "roofline_frac": ach / PEAK_LANE_OPS, "achieved_T_lane_op_s": ach / 1e12}
+    return {"el": el, "passes": passes_total, "kernel_ms": kernel_ms_total, "r": r, "tuning": tuning,
+            "el_sync": el_sync, "passes_sync": passes_sync, "steps": steps}
 
 
-def histogram_domain(dev, x_head, shape_head):
-    """Exact histogram-domain solve (FCM_DRIVER_HISTOGRAM) on the headline
-    volume and the 512x512x256 volume: one pass over the data, then the
+def small_workloads(dev, steps, launch, tune_cache):
+    """Configs small enough that a pass is latency-bound: the 200x200 slice
+    (the paper's 40 KB point) and the 128x128x64 volume (its ~1 MB point):
+    time to converge, voxel-iterations/s, time per pass against the ALU time
+    of a pass at the roofline; the slice's time per pass is the per-pass
+    latency floor of the persistent solve."""
+    import torch
+
+    from phantom import PhantomParams, phantom
+    out = {}
+    cases = (("slice_200x200", (200, 200), 1, "0.08 s at 40 KB (Table 3, Tesla C2050), context only"),
+             ("volume_128x128x64", (64, 128, 128), 2, "2.33 s at 1 MB (Table 3, Tesla C2050), context only"))
+    for name, shape, seed, ctx in cases:
+        x = torch.from_numpy(phantom(PhantomParams(shape=shape, seed=seed)).ravel()).to(dev)
+        n = x.numel()
+        st = solve_steps(dev, x, 4, 2.0, 1e-5, steps, 5, launch, True, tune_cache)
+        r = st["r"]
+        pps = st["passes"] / steps
+        launch_s = st["kernel_ms"] / steps * 1e-3
+        ent = roofline_entry(shape, n, 4, 2.0, pps, launch_s, st["tuning"], "fcm_persist_kernel<4>")
+        out[name] = {
+            "workload": f"ellipsoid-shell phantom {'x'.join(map(str, shape[::-1]))} ({n} voxels), seed {seed}, "
+                        f"sigma 8, bias 10%, C=4, m=2, eps=1e-5",
+            "iterations": r.iters, "passes_per_solve": pps,
+            "time_to_converge_ms": st["el"] * 1e3 / steps,
+            "time_to_converge_ms_host_waits_each_solve": st["el_sync"] * 1e3 / steps,
+            "voxel_iterations_per_s": n * st["passes"] / st["el"],
+            "us_per_pass": launch_s / pps * 1e6,
+            "alu_us_per_pass_at_roofline": n / alu_ceiling(4, 2.0) * 1e6,
+            "roofline": ent, "tuning": st["tuning"], "paper_context": ctx,
+        }
+    out["latency_floor_us_per_pass"] = out["slice_200x200"]["us_per_pass"]
+    return out
+
+
+def histogram_domain(dev, cases):
+    """Exact histogram-domain solve (FCM_DRIVER_HISTOGRAM) on the given
+    volumes ((name, device tensor) pairs): one pass over the data, then the
     iteration over grey levels; time to converge with labels, against the
     per-voxel persistent solve on the same handle configuration."""
     import torch
 
     from paper_1601_00072_amd import FCM
-    from phantom import PhantomParams, phantom
     out = {}
-    big = torch.from_numpy(phantom(PhantomParams(shape=(256, 512, 512), seed=3, sigma=9.0, bias=0.2)).ravel()).to(dev)
-    for name, x in (("1M volume " + "x".join(map(str, shape_head[::-1])), x_head), ("512x512x256 volume", big)):
+    for name, x in cases:
         labels = torch.empty_like(x)
         res = {}
         for drv in (3, 2):
@@ -298,7 +431,7 @@ def paper_protocol(dev, x, shape):
     with FCM(x, 4, eps=0.005) as f:
         timed_solves(f, 2, labels)
         el, _, _, r = timed_solves(f, 10, labels)
-    return {"workload": "1M volume " + "x".join(map(str, shape[::-1])) + ", C=4, m=2, eps=0.005",
+    return {"workload": "volume " + "x".join(map(str, shape[::-1])) + ", C=4, m=2, eps=0.005",
             "random_u": runs,
             "linspace": {"iterations": r.iters, "ms_to_converge": el / 10 * 1e3,
                          "centroids": [round(float(v), 4) for v in r.centroids]}}
@@ -328,17 +461,15 @@ def paper_design(dev, x, shape, fused_ms, eps):
     return out
 
 
-def quality(dev, shape, seed):
-    """Dice coefficient per tissue (Eq.5) of the GPU segmentation of the
-    headline volume and of the 512x512x256 volume against the phantoms'
-    tissue labels, and the time of the confusion-count + Dice kernels."""
+def quality(dev, cases):
+    """Dice coefficient per tissue (Eq.5) of the GPU segmentations of the
+    given phantoms ((name, PhantomParams) pairs) against their tissue labels,
+    and the time of the confusion-count + Dice kernels."""
     import torch
 
     from paper_1601_00072_amd import FCM, confusion, dice, rank_classes
-    from phantom import PhantomParams, phantom
+    from phantom import phantom
     out = {}
-    cases = (("1M volume " + "x".join(map(str, shape[::-1])), PhantomParams(shape=shape, seed=seed)),
-             ("512x512x256 volume", PhantomParams(shape=(256, 512, 512), seed=3, sigma=9.0, bias=0.2)))
     for name, p in cases:
         img, lab = phantom(p, with_labels=True)
         x = torch.from_numpy(img.ravel()).to(dev)
@@ -359,6 +490,7 @@ def quality(dev, shape, seed):
         us = e0.elapsed_time(e1) / reps * 1e3
         out[name] = {"dsc": dict(zip(("background", "CSF", "GM", "WM"), d.cpu().tolist())),
                      "us_confusion_and_dice": us, "confusion_GB_per_s": 2 * x.numel() / (us * 1e-6) / 1e9}
+        del x, truth, labels
     return out
 
 
@@ -384,7 +516,9 @@ def batched(dev, tune_cache):
         torch.cuda.synchronize()
         el_b = (time.perf_counter() - t0) / reps
     vox_passes = sum(a.size * r.passes for a, r in zip(xs, res))
-    # algorithmic lane-ops of every instance (its own C and pass count)
+    # algorithmic work of every instance at its own C and pass count: the
+    # fixed count's roofline time, and the library's own lane-op count
+    t_roof = sum(a.size * r.passes / alu_ceiling(c, 2.0) for a, c, r in zip(xs, Cs, res))
     ops = sum(a.size * (alg_lane_ops(c, 2.0, False) + (r.passes - 1) * alg_lane_ops(c, 2.0, True))
               for a, c, r in zip(xs, Cs, res))
     # per-instance launch loop: the single-instance solver, one instance after another
@@ -409,7 +543,8 @@ def batched(dev, tune_cache):
             "voxels": n, "max_iterations": max(r.iters for r in res),
             "ms_per_batch_solve": el_b * 1e3, "voxel_iterations_per_s": vox_passes / el_b,
             "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b,
-            "roofline_frac_wall": ops / el_b / PEAK_LANE_OPS,
+            "roofline_frac_wall": t_roof / el_b,
+            "roofline_frac_wall_library_count": ops / el_b / PEAK_LANE_OPS,
             "tiling": {"chunks_per_thread": cpt, "grid": bgrid}}
 
 
@@ -462,10 +597,11 @@ def learned_sets(workers: int):
             for name, shape, count, _ in spec}
 
 
-def learned(dev, sets, x_head, C, m, eps, steps):
+def learned(dev, sets, volumes, C, m, eps, steps):
     """Train the network on GPU-converged centroids of the training slices,
     then compare warm and plain starts on the held-out sets (one handle per
-    instance, and all in one batched launch) and on the headline volume."""
+    instance, and all in one batched launch) and on whole volumes
+    ((name, device tensor) pairs)."""
     import numpy as np
     import torch
 
@@ -489,26 +625,27 @@ def learned(dev, sets, x_head, C, m, eps, steps):
                      "batched": learn.evaluate_batch(net, x, sizes, C=4)}
         print(f"# learned: {name} done", file=sys.stderr, flush=True)
         del x
-    # the headline volume: time to converge, plain vs warm start
-    with FCM(x_head, C, m=m, eps=eps) as f:
-        rw, used, rp = f.solve_warm(net, check=True)
-        f.solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            f.reset()
+    # whole volumes: time to converge, plain vs warm start
+    for name, xv in volumes:
+        with FCM(xv, C, m=m, eps=eps) as f:
+            rw, used, rp = f.solve_warm(net, check=True)
             f.solve()
-        torch.cuda.synchronize()
-        tp = (time.perf_counter() - t0) / steps
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            f.solve_warm(net, check=False)
-        torch.cuda.synchronize()
-        tw = (time.perf_counter() - t0) / steps
-    out["headline_volume"] = {"iters_plain": rp.iters, "iters_warm": rw.iters, "warm_accepted": used,
-                              "rel_J_gap": (rw.J - rp.J) / rp.J, "ms_to_converge_plain": tp * 1e3,
-                              "ms_to_converge_warm": tw * 1e3,
-                              "warm_includes": "histogram + BF16 network + start post-processing + solve"}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                f.reset()
+                f.solve()
+            torch.cuda.synchronize()
+            tp = (time.perf_counter() - t0) / steps
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                f.solve_warm(net, check=False)
+            torch.cuda.synchronize()
+            tw = (time.perf_counter() - t0) / steps
+        out[name] = {"iters_plain": rp.iters, "iters_warm": rw.iters, "warm_accepted": used,
+                     "rel_J_gap": (rw.J - rp.J) / rp.J, "ms_to_converge_plain": tp * 1e3,
+                     "ms_to_converge_warm": tw * 1e3,
+                     "warm_includes": "histogram + BF16 network + start post-processing + solve"}
     net.close()
     return out
 
@@ -536,38 +673,27 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 5}))
         return
 
-    from paper_1601_00072_amd import FCM
     from phantom import PhantomParams, phantom
 
     shape = tuple(int(s) for s in args.shape.split(","))
-    x_np = phantom(PhantomParams(shape=shape, seed=args.seed))
+    params = PhantomParams(shape=shape, seed=args.seed, sigma=args.sigma, bias=args.bias)
+    x_np = phantom(params)
     n = x_np.size
     x = torch.from_numpy(x_np.ravel()).to(dev)
-    labels = torch.empty_like(x)
-    stream = torch.cuda.current_stream(dev)
     C, m, eps = args.clusters, args.m, args.eps
-
-    f = FCM(x, C, m=m, eps=eps, max_iter=300, timing=True, stream=stream)
-    f.set_tuning(launch=0 if args.launch == "cooperative" else 1)
-    tuned_ms = None
-    if not args.no_autotune:
-        _, tuned_ms = f.autotune(cache=args.tune_cache, reps=3)
-    timed_async(f, args.warmup, labels)
-    tuning = f.tuning
-    print(f"# warmup done, tuning {tuning}", file=sys.stderr, flush=True)
-    el, passes_total, kernel_ms_total, r = timed_async(f, args.steps, labels)
-    # the same solves one at a time, each waited for (fcm_solve + labels)
-    el_sync, passes_sync, _, _ = timed_solves(f, args.steps, labels)
-    f.close()
-    print(f"# timed {args.steps} solves: T={r.iters} status={r.status}", file=sys.stderr, flush=True)
+    wl = (f"ellipsoid-shell phantom {'x'.join(map(str, shape[::-1]))} ({n} voxels, uint8), seed {args.seed}, "
+          f"sigma {args.sigma:g}, bias {100 * args.bias:g}%, C={C}, m={m}, eps={eps}, max_iter=300, linspace init")
+    print(f"# headline: {wl}", file=sys.stderr, flush=True)
+    st = solve_steps(dev, x, C, m, eps, args.steps, args.warmup, args.launch, not args.no_autotune, args.tune_cache)
+    r, tuning, el = st["r"], st["tuning"], st["el"]
+    print(f"# timed {args.steps} solves: T={r.iters} status={r.status} tuning {tuning}", file=sys.stderr, flush=True)
 
     ms_per_step = el * 1e3 / args.steps
-    passes_per_solve = passes_total / args.steps
-    launch_s = kernel_ms_total / args.steps * 1e-3
-    achieved = roofline(n, C, m, passes_per_solve, launch_s)
+    passes_per_solve = st["passes"] / args.steps
+    launch_s = st["kernel_ms"] / args.steps * 1e-3
     out = {
         "metric": METRIC,
-        "value": n * passes_total / el,
+        "value": n * st["passes"] / el,
         "unit": "voxel-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -579,49 +705,39 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"ellipsoid-shell phantom {'x'.join(map(str, shape[::-1]))} ({n} voxels, uint8), seed "
-                        f"{args.seed}, sigma 8, bias 10%, C={C}, m={m}, eps={eps}, max_iter=300, linspace init",
-            "n_voxels": n, "C": C, "m": m, "eps": eps, "iterations": r.iters,
+            "workload": wl,
+            "n_voxels": n, "C": C, "m": m, "eps": eps, "iterations": r.iters, "status": r.status,
             "passes_per_solve": passes_per_solve,
             "time_to_converge_ms": ms_per_step,
             "step": "data-range pass + fused passes to convergence + labels, one persistent launch per step "
                     "(fcm_solve_async), steps enqueued back to back, one host wait for the timed run; "
                     "passes counted on the device",
-            "ms_per_step_host_waits_each_solve": el_sync * 1e3 / args.steps,
-            "value_host_waits_each_solve": n * passes_sync / el_sync,
+            "ms_per_step_host_waits_each_solve": st["el_sync"] * 1e3 / args.steps,
+            "value_host_waits_each_solve": n * st["passes_sync"] / st["el_sync"],
             "launch": args.launch,
             "tuning": tuning,
             "autotuned": not args.no_autotune,
-            "paper_context": "0.08 s at 40 KB and 2.33 s at 1 MB on a Tesla C2050 (Table 3), context only",
+            "precision": "FP32 memberships, Kahan-compensated FP32 partial sums, FP64 cross-block reduction and J",
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": f"fcm_persist_kernel<{C}>",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "T lane-op/s",
-            "frac": achieved / PEAK_LANE_OPS,
-            "traffic": recorded_traffic(shape, C, m, tuning),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "launch_avg_us": launch_s * 1e6,
-            "alg_lane_ops_per_voxel_pass": alg_lane_ops(C, m, True),
-        },
+        "roofline": roofline_entry(shape, n, C, m, passes_per_solve, launch_s, tuning, f"fcm_persist_kernel<{C}>"),
     }
     if not args.quick:
-        lv = large_volume(dev, args.tune_cache)
-        print(f"# large volume: {lv['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+        sm = small_workloads(dev, args.steps, args.launch, args.tune_cache)
+        print(f"# small workloads: floor {sm['latency_floor_us_per_pass']:.2f} us/pass", file=sys.stderr, flush=True)
         bt = batched(dev, args.tune_cache)
         print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
-        ln = learned(dev, sets, x, C, m, eps, args.steps)
-        hd = histogram_domain(dev, x, shape)
+        x1 = torch.from_numpy(phantom(PhantomParams(shape=(64, 128, 128), seed=2)).ravel()).to(dev)
+        ln = learned(dev, sets, (("volume_128x128x64", x1), ("volume_512x512x256", x)), C, m, eps,
+                     min(args.steps, 10))
+        hd = histogram_domain(dev, (("volume_128x128x64", x1), ("volume_512x512x256", x)))
         print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
-        q = quality(dev, shape, args.seed)
+        q = quality(dev, (("volume_128x128x64", PhantomParams(shape=(64, 128, 128), seed=2)), ("volume_512x512x256", params)))
         print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
-        pp = paper_protocol(dev, x, shape)
+        pp = paper_protocol(dev, x1, (64, 128, 128))
         print(f"# paper protocol: {pp}", file=sys.stderr, flush=True)
-        pd = paper_design(dev, x, shape, ms_per_step, eps)
+        pd = paper_design(dev, x1, (64, 128, 128), sm["volume_128x128x64"]["time_to_converge_ms"], eps)
         print(f"# paper design: {pd}", file=sys.stderr, flush=True)
-        out["extra"] = {"large_volume": lv, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
+        out["extra"] = {"small_workloads": sm, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
                         "segmentation_quality": q, "paper_protocol": pp, "paper_design_baseline": pd}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)

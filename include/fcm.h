@@ -45,6 +45,8 @@ extern "C" {
 #define FCM_ESTATE        (-4)  /* call out of order (e.g. labels before init) */
 #define FCM_ENUMERIC      (-5)  /* a non-finite centroid or objective appeared */
 #define FCM_EUNSUPPORTED  (-6)  /* configuration not built into this library */
+#define FCM_EIO           (-7)  /* a file could not be read or written, or does not hold
+                                   a network of the expected layout */
 
 #define FCM_MAX_CLUSTERS 8
 
@@ -106,7 +108,10 @@ extern "C" {
 #define FCM_LAUNCH_RESIDENT    1  /* default: ordinary launch of a grid no larger than the
                                      device holds at once.  Another kernel occupying the
                                      device can delay some blocks; a wait that exceeds the
-                                     time limit (5 s) ends the solve with FCM_EDEVICE */
+                                     time limit (5 s, fcm_set_wait_limit) ends the launch:
+                                     fcm_solve then solves again from the start in a
+                                     cooperative launch (fcm_solve_async reports
+                                     FCM_EDEVICE through fcm_solve_wait) */
 
 typedef struct fcm_params {
     int32_t n_clusters;           /* C, 2..FCM_MAX_CLUSTERS */
@@ -199,6 +204,20 @@ int fcm_solve_async(fcm_handle* h, uint8_t* d_labels);
  * passes committed on this handle since it was created (all drivers; restarts
  * from 0 after a recovered time-out), to count the work of pending solves. */
 int fcm_solve_wait(fcm_handle* h, fcm_result* out, int64_t* total_passes);
+
+/* Wall-clock limit of one cross-block wait of the persistent driver, in
+ * seconds (0 < seconds <= 60; default 5; 0 keeps the current limit), and
+ * recoveries (may be NULL): how many solves on this handle were run again in a
+ * cooperative launch.  A wait that reaches the limit ends the launch in every
+ * block (each wait also watches a shared abort word), and the solve reports
+ * FCM_EDEVICE -- except that fcm_solve (also inside fcm_solve_warm) runs a
+ * solve that began from its start, with the default resident launch
+ * (FCM_LAUNCH_RESIDENT), once more from the start in a cooperative launch,
+ * which the runtime makes co-resident, waiting at least the default limit;
+ * that result is then returned and counted here.  A limit far below the
+ * duration of a pass makes every wait give up: that is how the tests drive the
+ * failure path from the host.  FCM_EINVAL for a limit outside the range. */
+int fcm_set_wait_limit(fcm_handle* h, double seconds, int32_t* recoveries);
 
 /* Copy v^T (C doubles) to the host buffer out. */
 int fcm_centroids(fcm_handle* h, double* out);
@@ -339,6 +358,31 @@ int fcm_mlp_train(fcm_mlp* net, const float* d_hist, const float* d_target, int3
 
 void fcm_mlp_destroy(fcm_mlp* net);
 
+/* Persistence of a trained network (the warm start's only learned state).
+ * File layout, little-endian: a 64-byte header
+ *   char     magic[8]   "FCMMLP01"
+ *   uint32_t version    1
+ *   uint32_t dtype      0 (FP32 parameters)
+ *   int32_t  n_in, h1, h2, C   256, 128, 64, C
+ *   int64_t  n_params   fcm_mlp_param_count(C)
+ *   uint64_t seed       the seed the network was created with
+ *   uint64_t layout     FNV-1a 64 hash of the eight 32-bit words version, dtype,
+ *                       n_in, h1, h2, C, low and high half of n_params
+ *   uint64_t checksum   FNV-1a 64 hash of the parameter bytes
+ * followed by the n_params FP32 values of the flat vector (the order of
+ * fcm_mlp_get_params).  The Adam state is not saved.
+ * fcm_mlp_save writes the file (through a temporary file renamed over path,
+ * so a reader never sees half a file) and waits for the network's stream.
+ * Errors: FCM_EINVAL (null arguments), FCM_EIO (the file cannot be written).
+ * fcm_mlp_load replaces the parameters of a network with the same C (and, as
+ * fcm_mlp_set_params, clears its Adam state); it takes the file's seed.
+ * Errors: FCM_EINVAL (null arguments, or the file's C differs from the
+ * network's), FCM_EIO (unreadable or truncated file, wrong magic, version,
+ * dtype, layer sizes, layout hash or checksum); the network is unchanged on
+ * error. */
+int fcm_mlp_save(fcm_mlp* net, const char* path);
+int fcm_mlp_load(fcm_mlp* net, const char* path);
+
 /* Normalised 256-bin histograms (each row sums to 1) of the instances
  * d_x[offsets[i] .. offsets[i+1]) (offsets: count + 1 host values, starting
  * at 0, non-decreasing, every instance non-empty) into d_hist[count][256].
@@ -372,6 +416,31 @@ int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, 
  * fcm_batch_init.  Computes the histograms and runs the network on the
  * batch's stream (allocating their buffers on the first call). */
 int fcm_batch_set_start(fcm_batch* b, fcm_mlp* net, const uint8_t* use_learned);
+
+/* Warm-started batch solve with the fall-back rule of fcm_solve_warm, per
+ * instance.  check != 0: every instance is first solved from its own start
+ * (the plain results, copied to plain[count] if non-NULL); then the instances
+ * whose C equals the network's are solved from the network's start; warm
+ * instance i is kept only if its status is not FCM_ENUMERIC and J_warm <=
+ * J_plain (1 + 1e-6), and every instance that falls back is solved again from
+ * its own start in one final launch, so that labels and trajectories match the
+ * returned results.  check == 0: one launch from the learned starts.  out
+ * (count records) receives the returned results, used (count host bytes, may
+ * be NULL) 1 where the warm-started result is returned.  The batch keeps the
+ * starts of the returned results for later fcm_batch_solve calls
+ * (fcm_batch_set_start(b, NULL, NULL) restores the instances' own starts).
+ * Returns as fcm_batch_solve.  The plain start is the judge (Algorithm 1 from
+ * the instance's own v^0); the network only proposes v^0. */
+int fcm_batch_solve_warm(fcm_batch* b, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain,
+                         uint8_t* used);
+
+/* Training targets of the network from the last fcm_batch_solve:
+ * d_target[i * C + k] = the k-th smallest centroid of instance i's v^T,
+ * divided by 255 in FP64 and rounded to FP32 (the network's output scale).
+ * d_target: device, count * C floats, caller-owned.  Every instance must
+ * have C clusters (FCM_EINVAL otherwise); FCM_ESTATE before a solve.
+ * Enqueued on the batch's stream, not waited for. */
+int fcm_batch_targets(fcm_batch* b, int32_t C, float* d_target);
 
 /* ---- segmentation quality (Sec. 5.2.2, Eq.5) ----------------------------- */
 

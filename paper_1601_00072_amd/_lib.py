@@ -20,6 +20,7 @@ FCM_EDEVICE = -3
 FCM_ESTATE = -4
 FCM_ENUMERIC = -5
 FCM_EUNSUPPORTED = -6
+FCM_EIO = -7
 
 FCM_MAX_CLUSTERS = 8
 FCM_INIT_LINSPACE = 0
@@ -49,6 +50,7 @@ EXPORTS = (
     "fcm_mlp_forward", "fcm_mlp_loss_grad", "fcm_mlp_train", "fcm_mlp_destroy", "fcm_histogram",
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
     "fcm_confusion", "fcm_dice", "fcm_paper_solve", "fcm_solve_async", "fcm_solve_wait",
+    "fcm_mlp_save", "fcm_mlp_load", "fcm_batch_solve_warm", "fcm_batch_targets", "fcm_set_wait_limit",
 )
 
 
@@ -185,6 +187,17 @@ def load() -> ctypes.CDLL:
     lib.fcm_mlp_train.restype = ctypes.c_int
     lib.fcm_mlp_destroy.argtypes = [vp]
     lib.fcm_mlp_destroy.restype = None
+    lib.fcm_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    lib.fcm_mlp_save.restype = ctypes.c_int
+    lib.fcm_mlp_load.argtypes = [vp, ctypes.c_char_p]
+    lib.fcm_mlp_load.restype = ctypes.c_int
+    lib.fcm_batch_solve_warm.argtypes = [vp, vp, i32, ctypes.POINTER(FcmResult), ctypes.POINTER(FcmResult),
+                                         ctypes.POINTER(ctypes.c_uint8)]
+    lib.fcm_batch_solve_warm.restype = ctypes.c_int
+    lib.fcm_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
+    lib.fcm_set_wait_limit.restype = ctypes.c_int
+    lib.fcm_batch_targets.argtypes = [vp, i32, vp]
+    lib.fcm_batch_targets.restype = ctypes.c_int
     lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
     lib.fcm_histogram.restype = ctypes.c_int
     lib.fcm_paper_solve.argtypes = [vp, i64, ctypes.POINTER(FcmParams), vp, ctypes.POINTER(FcmResult), vp, vp, vp,

@@ -3,6 +3,8 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import os
+import sys
 
 import numpy as np
 
@@ -115,6 +117,14 @@ class FCM:
                                            ctypes.byref(t), ctypes.byref(ms)), "fcm_autotune")
         return {f: getattr(t, f) for f, _ in L.FcmTuning._fields_}, ms.value
 
+    def set_wait_limit(self, seconds: float = 0.0) -> int:
+        """Set the wall-clock limit of one cross-block wait (0 keeps it);
+        returns how many solves were run again in a cooperative launch after
+        a resident launch gave up (fcm_set_wait_limit)."""
+        rec = ctypes.c_int32()
+        self._check(self._lib.fcm_set_wait_limit(self._h, float(seconds), ctypes.byref(rec)), "fcm_set_wait_limit")
+        return rec.value
+
     # -- iteration --------------------------------------------------------------
     def reset(self):
         """Restart from v^0 on the same (possibly rewritten) input; no allocation."""
@@ -202,6 +212,10 @@ class FCM:
         self.close()
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime (and any profiler attached
+        # to it) may already be torn down: release nothing then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -304,28 +318,32 @@ class FCMBatch:
             raise FcmError(rc, "fcm_batch_set_start")
 
     def solve_warm(self, net: "MLP", check: bool = True):
-        """Warm-started batch solve with the fall-back rule per instance: with
-        check, instance i keeps its warm result only if J_warm <= J_plain (1 +
-        1e-6); the instances that fall back are solved again from their own
-        start in a final launch, so that labels and trajectories match the
-        returned results.  Returns (results, used_warm flags, plain results or
-        None); the batch keeps the starts of the returned results (set_start()
-        goes back to each instance's own init)."""
-        plain = None
-        if check:
-            self.set_start(None)
-            plain = self.solve()
-        self.set_start(net)
-        warm = self.solve()
-        used = np.array([c == net.C for c in self.C], dtype=bool)
-        if check:
-            ok = np.array([u and w.status != L.FCM_ENUMERIC and w.J <= p.J * (1.0 + 1e-6)
-                           for u, w, p in zip(used, warm, plain)], dtype=bool)
-            if not np.array_equal(ok, used):
-                self.set_start(net, ok)
-                warm = self.solve()
-            used = ok
-        return warm, used, plain
+        """Warm-started batch solve with the fall-back rule per instance
+        (fcm_batch_solve_warm).  Returns (results, used_warm flags, plain
+        results or None); the batch keeps the starts of the returned results
+        (set_start() goes back to each instance's own init)."""
+        out = (L.FcmResult * self.count)()
+        plain = (L.FcmResult * self.count)() if check else None
+        used = (ctypes.c_uint8 * self.count)()
+        rc = self._lib.fcm_batch_solve_warm(self._h, net._h, 1 if check else 0, out, plain, used)
+        if rc < 0 and rc != L.FCM_ENUMERIC:
+            raise FcmError(rc, "fcm_batch_solve_warm")
+        return ([_result(r) for r in out], np.array(used[:], dtype=bool),
+                None if plain is None else [_result(r) for r in plain])
+
+    def targets(self, C: int, out=None):
+        """Network training targets of the last solve (fcm_batch_targets):
+        each instance's centroids sorted ascending, / 255, as a float32 device
+        tensor [count, C]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.count, int(C)), dtype=torch.float32, device=self.x.device)
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != self.count * int(C):
+            raise ValueError("out must be a contiguous float32 tensor of count * C values")
+        rc = self._lib.fcm_batch_targets(self._h, int(C), ctypes.c_void_p(out.data_ptr()))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_targets")
+        return out
 
     def labels(self, out=None):
         import torch
@@ -357,6 +375,10 @@ class FCMBatch:
         self.close()
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime (and any profiler attached
+        # to it) may already be torn down: release nothing then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -541,10 +563,12 @@ class MLP:
         return out
 
     def save(self, path: str):
-        np.save(path, self.params())
+        """Write the parameters to a network file (fcm_mlp_save)."""
+        self._check(self._lib.fcm_mlp_save(self._h, os.fsencode(path)), "fcm_mlp_save")
 
     def load(self, path: str):
-        self.set_params(np.load(path, allow_pickle=False))
+        """Read parameters written by save() into this network (fcm_mlp_load)."""
+        self._check(self._lib.fcm_mlp_load(self._h, os.fsencode(path)), "fcm_mlp_load")
 
     @staticmethod
     def _dev2d(t, cols):
@@ -568,6 +592,10 @@ class MLP:
         self.close()
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime (and any profiler attached
+        # to it) may already be torn down: release nothing then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

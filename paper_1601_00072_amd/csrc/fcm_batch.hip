@@ -440,6 +440,32 @@ __global__ __launch_bounds__(kBlock) void fcm_batch_labels_kernel(BatchLabelArgs
     }
 }
 
+// Network training targets: instance i's v^T sorted ascending (insertion
+// sort of at most kMaxC values), each divided by 255 in FP64 and rounded once
+// to FP32.  One thread per instance.
+__global__ __launch_bounds__(kBlock) void fcm_batch_targets_kernel(const BatchRec* recs, int32_t I, int32_t C,
+                                                                    float* out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= I) return;
+    double v[kMaxC];
+    for (int k = 0; k < C; ++k) {
+        const double x = recs[i].vres[k];
+        int j = k;
+        while (j > 0 && v[j - 1] > x) {
+            v[j] = v[j - 1];
+            --j;
+        }
+        v[j] = x;
+    }
+    for (int k = 0; k < C; ++k) out[i * C + k] = (float)(v[k] / 255.0);
+}
+
+hipError_t launch_batch_targets(const BatchRec* recs, int32_t I, int32_t C, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(fcm_batch_targets_kernel, dim3((unsigned)((I + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       recs, I, C, out);
+    return hipGetLastError();
+}
+
 hipError_t batch_max_grid(int ncu, int* max_grid) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(

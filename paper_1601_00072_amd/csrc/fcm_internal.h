@@ -191,6 +191,7 @@ struct BatchLabelArgs {
 hipError_t batch_max_grid(int ncu, int* max_grid);
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_targets(const BatchRec* recs, int32_t I, int32_t C, float* out, hipStream_t s);
 
 // Histogram-domain solve (one block; fcm_levels.hip).
 struct LevelArgs {

@@ -13,8 +13,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fcm.h"
@@ -76,6 +78,7 @@ struct fcm_mlp {
     uint16_t* wb = nullptr;  // BF16 copy of theta for inference
     bool wb_stale = true;
     int step = 0;         // Adam steps taken
+    uint64_t seed = 0;    // creation seed (or the seed of the file loaded)
 
     // training workspace, `cap` rows
     int cap = 0;
@@ -178,6 +181,37 @@ int refresh_bf16(fcm_mlp* n, hipStream_t s) {
     return FCM_OK;
 }
 
+// ---- network files ----
+
+constexpr char kMagic[8] = {'F', 'C', 'M', 'M', 'L', 'P', '0', '1'};
+constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kDtypeF32 = 0;
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version, dtype;
+    int32_t n_in, h1, h2, C;
+    int64_t n_params;
+    uint64_t seed, layout, checksum;
+};
+static_assert(sizeof(FileHeader) == 64, "network file header is 64 bytes");
+
+// FNV-1a, 64-bit (Fowler, Noll and Vo): offset basis and prime as published
+uint64_t fnv1a(const void* data, size_t len, uint64_t h = 0xCBF29CE484222325ull) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < len; ++i) {
+        h ^= p[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+uint64_t layout_hash(const FileHeader& f) {
+    const uint32_t w[8] = {f.version, f.dtype, (uint32_t)f.n_in, (uint32_t)f.h1, (uint32_t)f.h2, (uint32_t)f.C,
+                           (uint32_t)((uint64_t)f.n_params & 0xFFFFFFFFu), (uint32_t)((uint64_t)f.n_params >> 32)};
+    return fnv1a(w, sizeof(w));
+}
+
 }  // namespace
 
 namespace fcm {
@@ -215,6 +249,7 @@ int fcm_mlp_create(fcm_mlp** out, int32_t C, uint64_t seed, void* stream) {
         return code;
     };
     n->C = C;
+    n->seed = seed;
     const Layout L(C);
     n->P = L.total;
     n->stream = (hipStream_t)stream;
@@ -258,6 +293,63 @@ int fcm_mlp_set_params(fcm_mlp* n, const float* in) {
     FCM_HIP(hipStreamSynchronize(n->stream));
     n->step = 0;
     n->wb_stale = true;
+    return FCM_OK;
+}
+
+int fcm_mlp_save(fcm_mlp* n, const char* path) {
+    if (!n || !path || !*path) return FCM_EINVAL;
+    std::vector<float> theta((size_t)n->P);
+    int rc = fcm_mlp_get_params(n, theta.data());
+    if (rc != FCM_OK) return rc;
+    FileHeader f{};
+    std::memcpy(f.magic, kMagic, sizeof(kMagic));
+    f.version = kFileVersion;
+    f.dtype = kDtypeF32;
+    f.n_in = kIn;
+    f.h1 = kH1;
+    f.h2 = kH2;
+    f.C = n->C;
+    f.n_params = n->P;
+    f.seed = n->seed;
+    f.layout = layout_hash(f);
+    f.checksum = fnv1a(theta.data(), sizeof(float) * theta.size());
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return FCM_EIO;
+    bool ok = std::fwrite(&f, sizeof(f), 1, fp) == 1 &&
+              std::fwrite(theta.data(), sizeof(float), theta.size(), fp) == theta.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return FCM_EIO;
+    }
+    return FCM_OK;
+}
+
+int fcm_mlp_load(fcm_mlp* n, const char* path) {
+    if (!n || !path || !*path) return FCM_EINVAL;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return FCM_EIO;
+    FileHeader f{};
+    std::vector<float> theta;
+    int rc = FCM_OK;
+    if (std::fread(&f, sizeof(f), 1, fp) != 1 || std::memcmp(f.magic, kMagic, sizeof(kMagic)) != 0 ||
+        f.version != kFileVersion || f.dtype != kDtypeF32 || f.n_in != kIn || f.h1 != kH1 || f.h2 != kH2 ||
+        f.C < 2 || f.C > FCM_MAX_CLUSTERS || f.n_params != Layout(f.C).total || f.layout != layout_hash(f)) {
+        rc = FCM_EIO;
+    } else if (f.C != n->C) {
+        rc = FCM_EINVAL;
+    } else {
+        theta.resize((size_t)f.n_params);
+        char extra;
+        if (std::fread(theta.data(), sizeof(float), theta.size(), fp) != theta.size() ||
+            std::fread(&extra, 1, 1, fp) != 0 || fnv1a(theta.data(), sizeof(float) * theta.size()) != f.checksum)
+            rc = FCM_EIO;
+    }
+    std::fclose(fp);
+    if (rc != FCM_OK) return rc;
+    if ((rc = fcm_mlp_set_params(n, theta.data())) != FCM_OK) return rc;
+    n->seed = f.seed;
     return FCM_OK;
 }
 

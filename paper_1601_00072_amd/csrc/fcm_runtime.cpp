@@ -95,6 +95,10 @@ struct fcm_handle {
     int ncu = 256;
     int coop = 0;               // cooperative launches supported
     uint64_t spin_ticks = 0;    // barrier wait limit in wall-clock ticks
+    uint64_t default_ticks = 0; // the default limit (kBarrierLimitSeconds)
+    uint64_t clock_khz = 100000;
+    bool coop_retry = false;    // the running solve is the cooperative retry of a resident launch
+    int32_t recoveries = 0;     // resident solves that gave up and were solved again cooperatively
     int mclass = kM2;
     float alpha = 1.f, mexp = 2.f;
 
@@ -193,7 +197,8 @@ PassArgs pass_args(const fcm_handle* h) {
     a.ghist = h->d_ghist ? h->d_ghist + (size_t)(h->ghist_sel & 1) * 256 * kHistCopies : nullptr;
     a.ghist_next = h->d_ghist ? h->d_ghist + (size_t)((h->ghist_sel + 1) & 1) * 256 * kHistCopies : nullptr;
     a.max_passes = 0;
-    a.spin_ticks = h->spin_ticks;
+    // the cooperative retry guarantees co-residency: it waits at least the default limit
+    a.spin_ticks = h->coop_retry ? std::max(h->spin_ticks, h->default_ticks) : h->spin_ticks;
     return a;
 }
 
@@ -389,7 +394,7 @@ int run_batch(fcm_handle* h, int batch) {
             FCM_HIP(hipEventRecord(h->ev[0], h->stream));
         }
         hipError_t e = launch_persist(a, h->p.n_clusters, h->mclass, h->tun.unroll, h->grid,
-                                      h->tun.launch == FCM_LAUNCH_COOPERATIVE, h->stream);
+                                      h->tun.launch == FCM_LAUNCH_COOPERATIVE || h->coop_retry, h->stream);
         if (e != hipSuccess) return dev_err(e, "persistent launch");
         h->pending_init = false;
         if (timing) FCM_HIP(hipEventRecord(h->ev[1], h->stream));
@@ -523,6 +528,7 @@ const char* fcm_strerror(int status) {
         case FCM_ESTATE: return "call out of order";
         case FCM_ENUMERIC: return "non-finite centroid or objective";
         case FCM_EUNSUPPORTED: return "configuration not supported";
+        case FCM_EIO: return "file could not be read or written, or has the wrong layout";
         default: return "unknown status";
     }
 }
@@ -563,7 +569,8 @@ int fcm_init(fcm_handle** out, const uint8_t* d_x, int64_t n, const fcm_params* 
     int clock_khz = 0;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clock_khz <= 0)
         clock_khz = 100000;
-    h->spin_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
+    h->clock_khz = (uint64_t)clock_khz;
+    h->spin_ticks = h->default_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
     h->tun.block = kBlock;
     h->tun.grid = 0;
     h->tun.unroll = 1;
@@ -647,6 +654,13 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
     if (!h || !out) return FCM_EINVAL;
     int rc = h->pending_init ? FCM_OK : read_state(h);
     if (rc != FCM_OK) return rc;
+    // A resident launch assumes that its whole grid is on the device at once;
+    // another kernel holding CUs can keep some blocks waiting until a wait
+    // gives up.  A solve that began from its start then runs once more from
+    // the start in a cooperative launch, whose grid the runtime makes
+    // co-resident (same iteration, same result).
+    const bool fresh = h->pending_init;
+    bool retried = false;
     // every pass either finishes the solve or advances the pass index, so
     // max_iter + 1 passes always suffice; the bound guards the host loop
     const int64_t total = (int64_t)h->p.max_iter + 1;
@@ -656,8 +670,24 @@ int fcm_solve(fcm_handle* h, fcm_result* out) {
                               ? (int)total
                               : h->tun.graph_k;
         rc = run_batch(h, batch);
-        if (rc != FCM_OK) return rc;
+        if (rc == FCM_EDEVICE && h->aborted && fresh && !retried && h->coop &&
+            h->tun.driver == FCM_DRIVER_PERSISTENT && h->tun.launch == FCM_LAUNCH_RESIDENT) {
+            retried = true;
+            if ((rc = enqueue_start(h)) != FCM_OK) return rc;
+            h->coop_retry = true;
+            budget = total + h->tun.graph_k;
+            continue;
+        }
+        if (rc != FCM_OK) {
+            h->coop_retry = false;
+            return rc;
+        }
         budget -= batch;
+    }
+    if (h->coop_retry) {
+        h->coop_retry = false;
+        ++h->recoveries;
+        last_error() = "a resident launch gave up waiting; the solve was run again in a cooperative launch";
     }
     fill_result(h, out);
     return out->status;
@@ -757,7 +787,9 @@ int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, 
     }
     rc = enqueue_start(h);
     if (rc == FCM_OK) rc = fcm_solve(h, &rw);
-    if (h->p.init == kInitLearnedFused && rc >= 0) h->ghist_sel ^= 1u;  // that launch zeroed the other buffer
+    // a launch that ran to its end (converged, out of iterations or non-finite)
+    // zeroed the other counter buffer: the next learned launch uses that one
+    if (h->p.init == kInitLearnedFused && (rc >= 0 || rc == FCM_ENUMERIC)) h->ghist_sel ^= 1u;
     h->p.init = own_init;
     h->dv0 = own_dv0;
     h->mlp_w = nullptr;
@@ -774,6 +806,14 @@ int fcm_solve_warm(fcm_handle* h, fcm_mlp* net, int32_t check, fcm_result* out, 
     *out = rw;
     if (used) *used = use;
     return out->status;
+}
+
+int fcm_set_wait_limit(fcm_handle* h, double seconds, int32_t* recoveries) {
+    if (!h) return FCM_EINVAL;
+    if (seconds != 0.0 && !(std::isfinite(seconds) && seconds > 0.0 && seconds <= 60.0)) return FCM_EINVAL;
+    if (seconds > 0.0) h->spin_ticks = std::max<uint64_t>(1, (uint64_t)(seconds * 1000.0 * (double)h->clock_khz));
+    if (recoveries) *recoveries = h->recoveries;
+    return FCM_OK;
 }
 
 int fcm_labels(fcm_handle* h, uint8_t* d_labels) {
@@ -1138,6 +1178,50 @@ int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
         else if (r.status != FCM_OK && worst == FCM_OK) worst = r.status;
     }
     return worst;
+}
+
+int fcm_batch_solve_warm(fcm_batch* b, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain,
+                         uint8_t* used) {
+    if (!b || !net || !out) return FCM_EINVAL;
+    const int C = mlp_clusters(net);
+    const size_t cnt = (size_t)b->count;
+    std::vector<fcm_result> rp;
+    std::vector<uint8_t> learned(cnt);
+    for (size_t i = 0; i < cnt; ++i) learned[i] = b->p[i].n_clusters == C ? 1 : 0;
+    int rc;
+    if (check) {  // the plain results: Algorithm 1 from each instance's own start
+        rp.resize(cnt);
+        if ((rc = fcm_batch_set_start(b, nullptr, nullptr)) != FCM_OK) return rc;
+        if ((rc = fcm_batch_solve(b, rp.data())) < 0 && rc != FCM_ENUMERIC) return rc;
+    }
+    if ((rc = fcm_batch_set_start(b, net, learned.data())) != FCM_OK) return rc;
+    if ((rc = fcm_batch_solve(b, out)) < 0 && rc != FCM_ENUMERIC) return rc;
+    if (check) {
+        bool differ = false;
+        std::vector<uint8_t> keep(cnt);
+        for (size_t i = 0; i < cnt; ++i) {
+            keep[i] = learned[i] && out[i].status != FCM_ENUMERIC && out[i].J <= rp[i].J * (1.0 + 1e-6);
+            differ |= keep[i] != learned[i];
+        }
+        if (differ) {  // fall back: one more launch so that the batch holds the returned results
+            if ((rc = fcm_batch_set_start(b, net, keep.data())) != FCM_OK) return rc;
+            if ((rc = fcm_batch_solve(b, out)) < 0 && rc != FCM_ENUMERIC) return rc;
+        }
+        learned.swap(keep);
+        if (plain) std::memcpy(plain, rp.data(), sizeof(fcm_result) * cnt);
+    }
+    if (used) std::memcpy(used, learned.data(), cnt);
+    return rc;
+}
+
+int fcm_batch_targets(fcm_batch* b, int32_t C, float* d_target) {
+    if (!b || !d_target || C < 2 || C > FCM_MAX_CLUSTERS) return FCM_EINVAL;
+    for (const fcm_params& q : b->p)
+        if (q.n_clusters != C) return FCM_EINVAL;
+    if (!b->solved) return FCM_ESTATE;
+    hipError_t e = launch_batch_targets(b->d_recs, b->count, C, d_target, b->stream);
+    if (e != hipSuccess) return dev_err(e, "launch_batch_targets");
+    return FCM_OK;
 }
 
 int fcm_batch_labels(fcm_batch* b, uint8_t* d_labels) {

@@ -30,20 +30,19 @@ def upload(instances, device):
 
 def targets(x, sizes, C: int = 4, m: float = 2.0, eps: float = 1e-5, max_iter: int = 300, chunk: int = 4096):
     """GPU-converged centroids / 255 (sorted) of every instance, float32
-    device tensor [count, C], and the results (in chunks of `chunk`
-    instances per batched launch)."""
+    device tensor [count, C] (fcm_batch_targets), and the results (in chunks
+    of `chunk` instances per batched launch)."""
     import torch
-    out, res = [], []
+    res = []
+    out = torch.empty((len(sizes), C), dtype=torch.float32, device=x.device)
     off = np.concatenate([[0], np.cumsum(sizes)])
     for c0 in range(0, len(sizes), chunk):
         c1 = min(len(sizes), c0 + chunk)
         sub = x[int(off[c0]):int(off[c1])]
         with FCMBatch(sub, sizes[c0:c1], [dict(n_clusters=C, m=m, eps=eps, max_iter=max_iter)] * (c1 - c0)) as b:
-            r = b.solve()
-        res.extend(r)
-        out.append(np.stack([np.sort(q.centroids) / 255.0 for q in r]))
-    t = torch.from_numpy(np.concatenate(out).astype(np.float32)).to(x.device)
-    return t, res
+            res.extend(b.solve())
+            b.targets(C, out[c0:c1])
+    return out, res
 
 
 def train(x, sizes, C: int = 4, epochs: int = 60, batch: int = 256, lr: float = 1e-3, seed: int = 1,

@@ -42,8 +42,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_strerror(lib):
     assert lib.fcm_version() == 10100
-    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
-        assert lib.fcm_strerror(code)
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
+        assert lib.fcm_strerror(code) != b"unknown status"
     assert lib.fcm_strerror(12345) == b"unknown status"
 
 
@@ -153,6 +153,21 @@ def test_learned_start_validation(lib):
     r = L.FcmResult()
     assert lib.fcm_solve_warm(None, None, 0, ctypes.byref(r), None, None) == L.FCM_EINVAL
     assert lib.fcm_batch_set_start(None, None, None) == L.FCM_EINVAL
+    assert lib.fcm_mlp_save(None, b"/tmp/x.fcmmlp") == L.FCM_EINVAL
+    assert lib.fcm_mlp_load(None, b"/tmp/x.fcmmlp") == L.FCM_EINVAL
+    assert lib.fcm_mlp_save(FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_mlp_load(FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_mlp_save(FAKE, b"") == L.FCM_EINVAL
+    out = (L.FcmResult * 2)()
+    used = (ctypes.c_uint8 * 2)()
+    assert lib.fcm_batch_solve_warm(None, FAKE, 1, out, None, used) == L.FCM_EINVAL
+    assert lib.fcm_batch_solve_warm(FAKE, None, 1, out, None, used) == L.FCM_EINVAL
+    assert lib.fcm_batch_solve_warm(FAKE, FAKE, 1, None, None, used) == L.FCM_EINVAL
+    assert lib.fcm_batch_targets(None, 4, FAKE) == L.FCM_EINVAL
+    assert lib.fcm_batch_targets(FAKE, 4, None) == L.FCM_EINVAL
+    assert lib.fcm_batch_targets(FAKE, 1, FAKE) == L.FCM_EINVAL
+    assert lib.fcm_batch_targets(FAKE, 9, FAKE) == L.FCM_EINVAL
+    assert lib.fcm_set_wait_limit(None, 1.0, None) == L.FCM_EINVAL
 
 
 def test_autotune_validation(lib):

@@ -338,3 +338,123 @@ def test_warm_start_in_kernel_and_launched(torch_dev, shape, driver, exchange):
         ora = ext
     P.compare(res, traj, ora, 1e-5, hist=h, m=2.0)
     P.check_labels(x, lab, ora.v[res.iters])
+
+
+def _fnv1a(data: bytes, h: int = 0xCBF29CE484222325) -> int:
+    """FNV-1a 64 (Fowler, Noll and Vo), written from its published definition."""
+    for b in data:
+        h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_network_file_round_trip_and_rejections(torch_dev, tmp_path):
+    """fcm_mlp_save / fcm_mlp_load: the documented header, bit-exact
+    parameters, and every malformed file refused with the network unchanged."""
+    import struct
+    from paper_1601_00072_amd import MLP
+    from paper_1601_00072_amd.api import FcmError
+    announce("network file")
+    torch, d = torch_dev
+    rng = np.random.default_rng(11)
+    src = MLP(4, seed=123)
+    theta = rng.standard_normal(src.n_params).astype(np.float32)
+    src.set_params(theta)
+    path = str(tmp_path / "net.fcmmlp")
+    src.save(path)
+    raw = open(path, "rb").read()
+    assert len(raw) == 64 + 4 * src.n_params
+    magic, version, dtype, n_in, h1, h2, C, n_params, seed, layout, checksum = struct.unpack("<8sIIiiiiqQQQ", raw[:64])
+    assert (magic, version, dtype, n_in, h1, h2, C, n_params, seed) == (b"FCMMLP01", 1, 0, 256, 128, 64, 4,
+                                                                          src.n_params, 123)
+    words = struct.pack("<8I", version, dtype, n_in, h1, h2, C, n_params & 0xFFFFFFFF, n_params >> 32)
+    assert layout == _fnv1a(words)
+    assert checksum == _fnv1a(raw[64:])
+    assert np.array_equal(np.frombuffer(raw[64:], dtype="<f4"), theta)
+
+    dst = MLP(4, seed=7)
+    before = dst.params()
+    dst.load(path)
+    assert np.array_equal(dst.params(), theta)
+    hist = dev(torch_dev, rand_hists(rng, 5))
+    assert torch.equal(dst.forward(hist, bf16=True), src.forward(hist, bf16=True))
+    dst.set_params(before)
+
+    def expect(status, data, net=dst):
+        bad = str(tmp_path / "bad.fcmmlp")
+        with open(bad, "wb") as fh:
+            fh.write(data)
+        with pytest.raises(FcmError) as e:
+            net.load(bad)
+        assert e.value.status == status
+        assert np.array_equal(net.params(), before if net is dst else net.params())
+
+    flip = bytearray(raw)
+    flip[64 + 4 * 1000] ^= 0x01
+    expect(-7, bytes(flip))                       # checksum
+    expect(-7, raw[:-4])                          # truncated
+    expect(-7, raw + b"\0")                       # trailing bytes
+    expect(-7, b"XCMMLP01" + raw[8:])             # magic
+    expect(-7, raw[:8] + struct.pack("<I", 2) + raw[12:])   # version
+    hdr = bytearray(raw)
+    hdr[24:28] = struct.pack("<i", 3)             # layer sizes changed without the layout hash
+    expect(-7, bytes(hdr))
+    with pytest.raises(FcmError) as e:
+        dst.load(str(tmp_path / "missing.fcmmlp"))
+    assert e.value.status == -7
+    with MLP(3, seed=0) as other:                 # a file of C = 4 into a network of C = 3
+        p3 = other.params()
+        with pytest.raises(FcmError) as e:
+            other.load(path)
+        assert e.value.status == -1
+        assert np.array_equal(other.params(), p3)
+    src.close()
+    dst.close()
+
+
+def test_batch_targets_are_sorted_centroids_over_255(torch_dev):
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCMBatch
+    from paper_1601_00072_amd.api import FcmError
+    announce("batch targets")
+    xs = [phantom(jittered_params((40 + 7 * i, 50), 900 + i)).ravel() for i in range(9)]
+    flat = torch.from_numpy(np.concatenate(xs)).to(d)
+    with FCMBatch(flat, [a.size for a in xs], [dict(n_clusters=4)] * len(xs)) as b:
+        with pytest.raises(FcmError):
+            b.targets(4)                          # before a solve
+        res = b.solve()
+        t = b.targets(4).cpu().numpy()
+        with pytest.raises(FcmError):
+            b.targets(3)                          # C differs from the instances'
+    want = np.stack([(np.sort(r.centroids) / 255.0).astype(np.float32) for r in res])
+    assert t.dtype == np.float32 and np.array_equal(t, want)
+
+
+def test_batch_warm_falls_back_per_instance(torch_dev):
+    """fcm_batch_solve_warm: an instance whose warm start reaches a worse
+    minimum returns its plain result (and the batch's labels are the plain
+    ones), its neighbours keep their warm results."""
+    torch, d = torch_dev
+    from paper_1601_00072_amd import FCMBatch
+    announce("batch warm fall-back")
+    tri = three_level_image()
+    two = np.concatenate([np.full(1500, 30, np.uint8), np.full(1500, 200, np.uint8)])
+    xs = [two, tri, two]
+    flat = torch.from_numpy(np.concatenate(xs)).to(d)
+    h_tri = fcm_hist.histogram(tri)
+    plain = fcm_hist.solve(h_tri, 2, 2.0, 1e-5, 300)
+    worse = fcm_hist.solve(h_tri, 2, 2.0, 1e-5, 300, v0=np.array([69.0, 240.0]))
+    assert worse.J[worse.T] > plain.J[plain.T] * (1 + 1e-3)
+    with const_net(2, [69.0, 240.0]) as net:
+        with FCMBatch(flat, [a.size for a in xs], [dict(n_clusters=2)] * 3) as b:
+            warm, used, pl = b.solve_warm(net, check=True)
+            lab = b.labels().cpu().numpy()
+            assert list(used) == [True, False, True]
+            assert warm[1].iters == pl[1].iters == plain.T
+            assert np.allclose(warm[1].centroids, plain.v[plain.T], rtol=1e-5)
+            off = two.size
+            assert np.array_equal(lab[off:off + tri.size], fcm_hist.level_labels(plain.v[plain.T])[tri])
+            for i in (0, 2):   # two levels: both starts end on the levels themselves
+                assert np.allclose(warm[i].centroids, [30.0, 200.0], rtol=1e-6)
+            w2, u2, p2 = b.solve_warm(net, check=False)
+            assert p2 is None and list(u2) == [True, True, True]
+            assert w2[1].iters == worse.T and np.allclose(w2[1].centroids, worse.v[worse.T], rtol=1e-5)

@@ -67,6 +67,7 @@ def test_slice_200x200_c4_m2(torch_dev):
     x = phantom_2d(200, 200, seed=1)
     res, ora, err, amb = check_against_literal(torch_dev, x, 4)
     assert res.status == 0 and res.iters == ora.T
+    assert amb == 0
     print("errors", err, "ambiguous levels", amb, "T", res.iters)
 
 
@@ -75,6 +76,7 @@ def test_volume_64x128x128_c4_m2(torch_dev):
     x = phantom_3d(64, 128, 128, seed=2)
     res, ora, err, amb = check_against_literal(torch_dev, x, 4)
     assert res.status == 0
+    assert amb == 0
     print("errors", err, "ambiguous levels", amb, "T", res.iters)
 
 
@@ -303,6 +305,7 @@ def test_volume_181x217x181(torch_dev, sigma, C, m, kahan):
     announce("volume 181x217x181 sigma", sigma, "C", C, "m", m, "kahan_only", kahan)
     x = phantom(PhantomParams(shape=(181, 217, 181), seed=3, sigma=sigma, bias=0.2))
     res, err, amb = check_against_levels(torch_dev, x, C, m, kahan_only=kahan)
+    assert amb == 0
     print("T", res.iters, "errors", err, "ambiguous", amb)
 
 
@@ -310,4 +313,5 @@ def test_volume_512x512x256(torch_dev):
     announce("volume 512x512x256 sigma 9, C=4 m=2")
     x = phantom(PhantomParams(shape=(256, 512, 512), seed=3, sigma=9.0, bias=0.2))
     res, err, amb = check_against_levels(torch_dev, x, 4, 2.0)
+    assert amb == 0
     print("T", res.iters, "errors", err, "ambiguous", amb)
