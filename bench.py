@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extras to run (small,batched,learned,histogram,quality,protocol,design)")
     ap.add_argument("--launch", choices=("cooperative", "resident"), default="resident",
                     help="launch of the persistent solve kernel")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
@@ -653,7 +655,8 @@ def learned(dev, sets, volumes, C, m, eps, steps):
 def main():
     args = parse()
     sets = None
-    if not args.quick and not args.copy_probe and args.gpus == 1:
+    if (not args.quick and not args.copy_probe and args.gpus == 1
+            and (args.extras == "all" or "learned" in args.extras.split(","))):
         t0 = time.perf_counter()
         sets = learned_sets(min(16, os.cpu_count() or 1))
         print(f"# learned-start data generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -722,23 +725,36 @@ def main():
         "roofline": roofline_entry(shape, n, C, m, passes_per_solve, launch_s, tuning, f"fcm_persist_kernel<{C}>"),
     }
     if not args.quick:
-        sm = small_workloads(dev, args.steps, args.launch, args.tune_cache)
-        print(f"# small workloads: floor {sm['latency_floor_us_per_pass']:.2f} us/pass", file=sys.stderr, flush=True)
-        bt = batched(dev, args.tune_cache)
-        print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+        want = set(args.extras.split(",")) if args.extras != "all" else {
+            "small", "batched", "learned", "histogram", "quality", "protocol", "design"}
+        ex = {}
         x1 = torch.from_numpy(phantom(PhantomParams(shape=(64, 128, 128), seed=2)).ravel()).to(dev)
-        ln = learned(dev, sets, (("volume_128x128x64", x1), ("volume_512x512x256", x)), C, m, eps,
-                     min(args.steps, 10))
-        hd = histogram_domain(dev, (("volume_128x128x64", x1), ("volume_512x512x256", x)))
-        print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
-        q = quality(dev, (("volume_128x128x64", PhantomParams(shape=(64, 128, 128), seed=2)), ("volume_512x512x256", params)))
-        print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
-        pp = paper_protocol(dev, x1, (64, 128, 128))
-        print(f"# paper protocol: {pp}", file=sys.stderr, flush=True)
-        pd = paper_design(dev, x1, (64, 128, 128), sm["volume_128x128x64"]["time_to_converge_ms"], eps)
-        print(f"# paper design: {pd}", file=sys.stderr, flush=True)
-        out["extra"] = {"small_workloads": sm, "batched": bt, "learned_warm_start": ln, "histogram_domain": hd,
-                        "segmentation_quality": q, "paper_protocol": pp, "paper_design_baseline": pd}
+        if "small" in want or "design" in want:
+            ex["small_workloads"] = sm = small_workloads(dev, args.steps, args.launch, args.tune_cache)
+            print(f"# small workloads: floor {sm['latency_floor_us_per_pass']:.2f} us/pass", file=sys.stderr,
+                  flush=True)
+        if "batched" in want:
+            ex["batched"] = bt = batched(dev, args.tune_cache)
+            print(f"# batch: {bt['ms_per_batch_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+        if "learned" in want and sets is not None:
+            ex["learned_warm_start"] = learned(dev, sets, (("volume_128x128x64", x1), ("volume_512x512x256", x)),
+                                               C, m, eps, min(args.steps, 10))
+        if "histogram" in want:
+            ex["histogram_domain"] = hd = histogram_domain(dev, (("volume_128x128x64", x1), ("volume_512x512x256", x)))
+            print(f"# histogram domain: {hd}", file=sys.stderr, flush=True)
+        if "quality" in want:
+            ex["segmentation_quality"] = q = quality(dev, (("volume_128x128x64", PhantomParams(shape=(64, 128, 128),
+                                                                                               seed=2)),
+                                                           ("volume_512x512x256", params)))
+            print(f"# segmentation quality: {q}", file=sys.stderr, flush=True)
+        if "protocol" in want:
+            ex["paper_protocol"] = pp = paper_protocol(dev, x1, (64, 128, 128))
+            print(f"# paper protocol: {pp}", file=sys.stderr, flush=True)
+        if "design" in want:
+            ex["paper_design_baseline"] = pd = paper_design(dev, x1, (64, 128, 128),
+                                                            sm["volume_128x128x64"]["time_to_converge_ms"], eps)
+            print(f"# paper design: {pd}", file=sys.stderr, flush=True)
+        out["extra"] = ex
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, C, m, eps, args.cpu_budget_s)
     print(json.dumps(out), flush=True)

@@ -90,16 +90,13 @@ extern "C" {
 #define FCM_EXCHANGE_LEADER    1  /* block 0 reduces and broadcasts the decision */
 #define FCM_EXCHANGE_ALLGATHER 2  /* every block reduces every partial row itself */
 #define FCM_EXCHANGE_XCD       3  /* two levels: the blocks sharing an XCD (blocks are dealt to
-                                     the 8 XCDs in turn) combine their rows through that XCD's
-                                     L2, one block per XCD publishes an FP64 row, and every
-                                     block adds the 8 XCD rows itself (no broadcast).  The
-                                     dealing is checked in the data-range pass of each solve;
-                                     where it differs, and for launches that continue a solve,
-                                     the leader exchange is used.  The in-XCD step relies on the
-                                     XCD's L2 making a workgroup-scope store visible to an
-                                     agent-scope load of another block on that XCD (measured on
-                                     MI355X); where it did not, a wait would end at its time
-                                     limit with FCM_EDEVICE.  Not with FCM_F_KAHAN_ONLY */
+                                     the 8 XCDs in turn) combine their rows in one block of that
+                                     XCD, which publishes an FP64 row; every block adds the 8
+                                     XCD rows itself (no broadcast).  Every exchange word is
+                                     stored and read with agent scope.  The dealing is checked in
+                                     the data-range pass of each solve; where it differs, and for
+                                     launches that continue a solve, the leader exchange is used.
+                                     Not with FCM_F_KAHAN_ONLY */
 
 /* how the persistent driver launches its kernel */
 #define FCM_LAUNCH_COOPERATIVE 0  /* hipLaunchCooperativeKernel: the runtime guarantees
@@ -242,14 +239,29 @@ typedef struct fcm_batch fcm_batch;
 
 /* Validates everything before any HIP call (FCM_EINVAL), allocates the
  * workspace (tile table, per-instance state and history), enqueues nothing.
- * Needs cooperative launches (FCM_EUNSUPPORTED otherwise). */
+ * The solve is one ordinary launch: its blocks take tiles of whichever
+ * instance has work ready and never wait for one another's work in
+ * progress, so the grid need not be resident at once. */
 int fcm_batch_init(fcm_batch** b, const uint8_t* d_x, const int64_t* offsets, int32_t count,
                    const fcm_params* params, void* stream);
 
-/* Tile size: chunks_per_thread 16-voxel chunks per thread and tile (1..64;
- * a tile is 256 threads wide), and the launch grid (0 = as many blocks as fit
- * on the device).  Rebuilds the tile table. */
+/* Tile size: chunks_per_thread 16-voxel chunks per thread and tile (1..64,
+ * default 8; a tile is 256 threads wide; an instance that would need more
+ * than 24,576 tiles gets larger ones), and the launch grid (0 = as many blocks
+ * as fit on the device).  Rebuilds the tile table.  The tiling fixes the
+ * order in which an instance's partial sums are added, so results are
+ * reproducible for a given tiling (and differ between tilings by FP32
+ * rounding only). */
 int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid);
+
+/* Tiles of the later passes: from pass from_pass on (>= 0; default 48) every
+ * instance runs on a second, finer tile set of chunks_per_thread chunks per
+ * thread (1..64; default 2).  Few instances remain by then, and each pass of
+ * the longest solves lies on the launch's critical path, so more, smaller
+ * tiles let more blocks share it; the early passes keep the coarse tiles and
+ * their lower per-tile cost.  The switch depends on the pass index only, so
+ * results stay reproducible.  Rebuilds the tile table. */
+int fcm_batch_set_tail_tiling(fcm_batch* b, int32_t from_pass, int32_t chunks_per_thread);
 
 /* Solve every instance from its v^0; waits for the stream; out[i] (count
  * records) receives instance i's result.  Returns FCM_OK if every instance
@@ -263,6 +275,13 @@ int fcm_batch_labels(fcm_batch* b, uint8_t* d_labels);
 
 /* History of instance inst (as fcm_trajectory). */
 int fcm_batch_trajectory(fcm_batch* b, int32_t inst, int32_t t, double* v_out, double* delta, double* J);
+
+/* Timeline of instance inst in the last solve: us[0] = microseconds from the
+ * start of the launch until the instance's data range and v^0 were
+ * committed, us[1 + p] = until pass p was committed (device wall clock), for
+ * the first min(cap, passes + 1) phases; count (may be NULL) receives
+ * passes + 1.  FCM_ESTATE before a solve. */
+int fcm_batch_timeline(fcm_batch* b, int32_t inst, double* us, int32_t cap, int32_t* count);
 
 void fcm_batch_destroy(fcm_batch* b);
 

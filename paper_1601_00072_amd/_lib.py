@@ -51,6 +51,7 @@ EXPORTS = (
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
     "fcm_confusion", "fcm_dice", "fcm_paper_solve", "fcm_solve_async", "fcm_solve_wait",
     "fcm_mlp_save", "fcm_mlp_load", "fcm_batch_solve_warm", "fcm_batch_targets", "fcm_set_wait_limit",
+    "fcm_batch_timeline", "fcm_batch_set_tail_tiling",
 )
 
 
@@ -161,6 +162,8 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_init.restype = ctypes.c_int
     lib.fcm_batch_set_tiling.argtypes = [vp, i32, i32]
     lib.fcm_batch_set_tiling.restype = ctypes.c_int
+    lib.fcm_batch_set_tail_tiling.argtypes = [vp, i32, i32]
+    lib.fcm_batch_set_tail_tiling.restype = ctypes.c_int
     lib.fcm_batch_solve.argtypes = [vp, ctypes.POINTER(FcmResult)]
     lib.fcm_batch_solve.restype = ctypes.c_int
     lib.fcm_batch_labels.argtypes = [vp, vp]
@@ -196,6 +199,8 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_solve_warm.restype = ctypes.c_int
     lib.fcm_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
     lib.fcm_set_wait_limit.restype = ctypes.c_int
+    lib.fcm_batch_timeline.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
+    lib.fcm_batch_timeline.restype = ctypes.c_int
     lib.fcm_batch_targets.argtypes = [vp, i32, vp]
     lib.fcm_batch_targets.restype = ctypes.c_int
     lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]

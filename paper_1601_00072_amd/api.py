@@ -281,10 +281,16 @@ class FCMBatch:
             self._h = None
             raise FcmError(rc, "fcm_batch_init")
 
-    def set_tiling(self, chunks_per_thread: int = 4, grid: int = 0):
+    def set_tiling(self, chunks_per_thread: int = 8, grid: int = 0):
         rc = self._lib.fcm_batch_set_tiling(self._h, int(chunks_per_thread), int(grid))
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_set_tiling")
+
+    def set_tail_tiling(self, from_pass: int = 48, chunks_per_thread: int = 2):
+        """Finer tiles from pass `from_pass` on (fcm_batch_set_tail_tiling)."""
+        rc = self._lib.fcm_batch_set_tail_tiling(self._h, int(from_pass), int(chunks_per_thread))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_set_tail_tiling")
 
     def solve(self):
         out = (L.FcmResult * self.count)()
@@ -353,6 +359,21 @@ class FCMBatch:
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_labels")
         return out
+
+    def timeline(self, i: int):
+        """Microseconds from the launch start until instance i committed its
+        data range (entry 0) and each pass p (entry 1 + p) in the last solve
+        (fcm_batch_timeline)."""
+        cnt = ctypes.c_int32()
+        rc = self._lib.fcm_batch_timeline(self._h, int(i), None, 0, ctypes.byref(cnt))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_timeline")
+        us = np.empty(cnt.value, dtype=np.float64)
+        rc = self._lib.fcm_batch_timeline(self._h, int(i), us.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          cnt.value, None)
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_timeline")
+        return us
 
     def trajectory(self, i: int, t: int):
         C = self.C[i]

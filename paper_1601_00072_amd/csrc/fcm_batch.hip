@@ -1,32 +1,44 @@
 // Batched solver: many instances (slices and volumes of uneven size, each
-// with its own C, m, eps and max_iter) converge in one cooperative launch.
+// with its own C, m, eps and max_iter) converge in one persistent launch.
 //
 // The input is a concatenation of instances; the host cuts every instance
-// into tiles of 16-voxel chunks.  The launch runs lock-step sweeps; sweep s
-// runs pass s of every unfinished instance:
-//   tiles   every block takes tiles t = block, block + G, ...; for each it
-//           reads the instance's decision of sweep s - 1 (skipping finished
-//           instances), runs the fused pass over the tile's voxels and writes
-//           the tile's partial row;
-//   owners  block i mod G owns instance i: it reduces the instance's tile rows
-//           in tile order (FP64, or compensated FP32), applies Eq.3 and the
-//           stopping rule of Algorithm 1, records the history and publishes
-//           the decision (centroids of the next pass, done flag).
-// Tile work of sweep s needs only decisions of sweep s - 1, and owner work of
-// sweep s needs only tile rows of sweep s, which every block writes before it
-// starts owner work, so no wait can be circular.  Values travel as tagged
-// 64-bit words (see fcm_device.h); every wait is bounded by a wall-clock limit
-// and an abort word.  A finished instance's tiles are skipped from then on;
-// the launch ends when no instance is left.
+// into tiles of 16-voxel chunks (a coarse set, and a fine set for the later
+// passes).  Each instance runs the same phases as a single solve -- phase 0
+// finds its grey-level range and v^0, phase p + 1 is fused pass p -- at its
+// own pace; no instance waits for another.  An instance's control word
+// (fcm_internal.h) counts the tiles of its current phase handed out and
+// finished:
+//   claim   a free block takes a tile of the instance it worked on last if
+//           that has tiles open, else of the first instance with open tiles
+//           in its own rotation order (blocks start their rotations at
+//           spread positions), with one atomic add on the control word; it
+//           reads the phase's decision (tagged words) and runs the tile:
+//           min/max for phase 0, the fused pass (Eq.4, Eq.3 sums, Eq.1 term,
+//           change) otherwise, writing one tagged partial row;
+//   arrive  a second atomic add counts the tile as finished; the block that
+//           finishes the phase's last tile reduces the instance's rows in tile
+//           order (FP64, or compensated FP32), applies Eq.3 and the stopping
+//           rule of Algorithm 1, records the history, then opens the next
+//           phase with its tile 0 already taken by itself: it goes on with
+//           that tile at once, with the decision still in LDS, and publishes
+//           the decision only for the other blocks that will take the
+//           phase's other tiles.  A phase with a single tile therefore never
+//           leaves the block: its row is reduced from LDS, with no arrival and
+//           no global read, so a small instance is solved by one block at the
+//           speed of its arithmetic.
+// A block waits only for tagged words that a finished tile or phase has
+// already written (bounded polls), never for work of another block in
+// progress, so no grid-wide residency is needed; the rows are reduced in the
+// same order whichever blocks ran the tiles, so results are reproducible run
+// to run.  Every wait is bounded by a wall-clock limit and an abort word.
+// Blocks leave when no instance is left, or once they outnumber the tiles of
+// the unfinished instances.
 
 #include "fcm_device.h"
 
 namespace fcm {
 
 namespace {
-
-// round counters compare as signed differences, so they may wrap
-__device__ __forceinline__ bool reached(uint32_t v, uint32_t target) { return (int32_t)(v - target) >= 0; }
 
 // Wait until the K words at src carry `round` (same scheme as poll_tagged:
 // a few whole-group polls, then the last word with back-off).
@@ -83,65 +95,81 @@ struct BatchRows {
     }
 };
 
-// Decision of instance i for the round `round`, read by one thread.  Returns
-// 1 when the instance is running (centroids in vn/vo, pass in p), 0 when it
-// has finished, -1 when the wait was abandoned.  A finished flag counts only
-// if it was written in this solve (tag >= base, the solve's first round).
-__device__ __forceinline__ int read_decision(const uint64_t* dec, uint32_t round, uint32_t base, BatchSync* sy,
-                                             uint64_t limit, float* vn, float* vo, int& p) {
-    const uint64_t t0 = wall_clock64();
-    int spins = 0;
-    uint32_t raw[kBatchDecWords];
-    const uint64_t* ctl = dec + 2 * kMaxC;
-    while (true) {
-        // a few whole-group polls (one round trip each), then the control
-        // word (written last) with back-off
-        bool all = true;
-        uint32_t ctl_tag = 0;
+// The one row of a phase that has a single tile, kept in LDS by the block
+// that runs it (same folded values as a tagged row).
+template <int K>
+struct LocalRows {
+    float* W;
+    __device__ __forceinline__ void put_pair(int q, float s, float c) const { W[q] = s - c; }
+    __device__ __forceinline__ void put_max(int q, float m) const { W[q] = m; }
+    template <int R>
+    __device__ __forceinline__ bool get(int, float (&v)[R]) const {
+        static_assert(R == 2 * (K - 1) + 1, "row format");
 #pragma unroll
-        for (int r = 0; r < kBatchDecWords; ++r) {
-            const uint64_t w = __hip_atomic_load(dec + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            all = all && (uint32_t)(w >> 32) == round;
-            raw[r] = (uint32_t)w;
-            ctl_tag = (uint32_t)(w >> 32);  // the last word is the control word
+        for (int q = 0; q < K - 1; ++q) {
+            v[2 * q] = W[q];
+            v[2 * q + 1] = 0.f;
         }
-        if ((raw[kBatchDecWords - 1] & 1u) && reached(ctl_tag, base) && reached(round, ctl_tag)) return 0;
-        if (all) break;
-        if (poll_expired(sy, t0, limit, spins)) return -1;
-        if (spins < kFastPolls) continue;
-        while (true) {
-            const uint64_t w = __hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t tag = (uint32_t)(w >> 32);
-            if (((uint32_t)w & 1u) && reached(tag, base) && reached(round, tag)) return 0;  // finished earlier
-            if (tag == round) break;
-            if (poll_expired(sy, t0, limit, spins)) return -1;
-        }
+        v[R - 1] = W[K - 1];
+        return true;
     }
-    for (int k = 0; k < kMaxC; ++k) {
-        vn[k] = __builtin_bit_cast(float, raw[k]);
-        vo[k] = __builtin_bit_cast(float, raw[kMaxC + k]);
-    }
-    p = (int)(raw[2 * kMaxC] >> 1);
-    return (raw[2 * kMaxC] & 1u) ? 0 : 1;
+};
+
+// The decision a block's tile is computed with (a copy in LDS): v^p and
+// v^(p-1) in FP32, p, and v^p in FP64 for completing the pass.
+struct Decision {
+    float vn[kMaxC], vo[kMaxC];
+    double v64[kMaxC];
+    int p;
+};
+
+// The tile set of a phase: coarse for phase 0 and the early passes, fine
+// (more, smaller tiles) from pass fine_from on, where few instances remain
+// and each pass of the longest ones is on the critical path.  A function of
+// the phase only, so every run adds an instance's partial sums in the same
+// order.
+__device__ __forceinline__ int tile_set(const BatchArgs& a, uint32_t phase) {
+    return phase >= 1u && (int)phase - 1 >= a.fine_from ? 1 : 0;
 }
 
-__device__ __forceinline__ void write_decision(uint64_t* dec, uint32_t round, const float* vn, const float* vo,
-                                               int C, int p, int done) {
-    for (int k = 0; k < kMaxC; ++k) {
+__device__ __forceinline__ int phase_tiles(const BatchArgs& a, int i, uint32_t phase) {
+    return a.ntiles[2 * i + tile_set(a, phase)];
+}
+
+// Decision of pass p for the other blocks (tagged words, fcm_internal.h),
+// written by lanes 0 .. kMaxC of the calling block.
+__device__ __forceinline__ void publish_decision(uint64_t* dec, uint32_t round, const float* vn, const float* vo,
+                                                 const double* v64, int C, int p) {
+    const int k = threadIdx.x;
+    if (k < kMaxC) {
+        const uint64_t bits = k < C ? __builtin_bit_cast(uint64_t, v64[k]) : 0ull;
         store_tagged(dec + k, round, __builtin_bit_cast(uint32_t, k < C ? vn[k] : 0.f));
         store_tagged(dec + kMaxC + k, round, __builtin_bit_cast(uint32_t, k < C ? vo[k] : 0.f));
+        store_tagged(dec + kBatchDecF64 + 2 * k, round, (uint32_t)bits);
+        store_tagged(dec + kBatchDecF64 + 2 * k + 1, round, (uint32_t)(bits >> 32));
+    } else if (k == kMaxC) {
+        store_tagged(dec + 2 * kMaxC, round, (uint32_t)p);
     }
-    store_tagged(dec + 2 * kMaxC, round, ((uint32_t)p << 1) | (uint32_t)(done != 0));
 }
 
-// Fused pass over one tile's voxels (thread-strided chunks, plus the
-// instance's ragged voxels on its first tile).
+// Fused pass over one tile's voxels (thread-strided chunks, the next chunk
+// loaded while the current one is computed, plus the instance's ragged
+// voxels on its first tile).
 template <int C, int FORM, bool OLD>
 __device__ __forceinline__ void tile_body(const uint8_t* xi, const BatchInst& in, const BatchTile& tl,
                                           const float (&vn)[C], const float (&vo)[C], const Consts& kc, Acc<C>& acc) {
     const int tid = threadIdx.x;
     const uint4* body = reinterpret_cast<const uint4*>(xi + in.head);
-    for (int64_t c = tl.c0 + tid; c < tl.c1; c += kBlock) chunk16<C, FORM, OLD>(body[c], vn, vo, kc, acc);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    int64_t c = tl.c0 + tid;
+    uint4 cur = c < tl.c1 ? body[c] : z;
+    while (c < tl.c1) {
+        const int64_t cn = c + kBlock;
+        const uint4 nx = cn < tl.c1 ? body[cn] : z;
+        chunk16<C, FORM, OLD>(cur, vn, vo, kc, acc);
+        cur = nx;
+        c = cn;
+    }
     if (tl.ragged) {
         const int64_t tail0 = in.head + 16 * in.nbody;
         const int64_t nr = in.head + (in.n - tail0);
@@ -155,15 +183,18 @@ __device__ __forceinline__ void tile_body(const uint8_t* xi, const BatchInst& in
     }
 }
 
+// One tile of fused pass d.p; its partial row goes to the tagged row buffer,
+// or to LDS (`lrow`) when the phase has a single tile.
 template <int C>
-__device__ void tile_pass(const BatchArgs& a, int64_t t, const BatchInst& in, const BatchTile& tl, int p,
-                          const float* svn, const float* svo, uint32_t round) {
+__device__ __forceinline__ void tile_pass(const BatchArgs& a, int64_t t, const BatchInst& in, const BatchTile& tl,
+                                          const Decision& d, uint32_t round, float* lrow) {
     float vn[C], vo[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        vn[k] = svn[k];
-        vo[k] = svo[k];
+        vn[k] = d.vn[k];
+        vo[k] = d.vo[k];
     }
+    const int p = d.p;
     const uint8_t* xi = a.x + in.base;
     const Consts kc{in.alpha, in.mexp};
     Acc<C> acc;
@@ -185,202 +216,426 @@ __device__ void tile_pass(const BatchArgs& a, int64_t t, const BatchInst& in, co
         else
             tile_body<C, kNormLog, true>(xi, in, tl, vn, vo, kc, acc);
     }
-    const BatchRows<2 * C + 2> rows{a.rows, round, a.sync, 0, 0, t};
-    write_partial_row<C>(acc, rows);
+    if (lrow) {
+        write_partial_row<C>(acc, LocalRows<2 * C + 2>{lrow});
+    } else {
+        const BatchRows<2 * C + 2> rows{a.rows, round, a.sync, 0, 0, t};
+        write_partial_row<C>(acc, rows);
+    }
 }
 
-// Owner step of instance i for pass p: reduce its tile rows, decide, record,
-// publish.  Returns false (all threads) if a wait was abandoned.
-template <int C>
-__device__ bool owner_step(const BatchArgs& a, int i, const BatchInst& in, int p, uint32_t round) {
-    __shared__ Reduced<C> s_r;
-    const BatchRows<2 * C + 2> rows{a.rows + (int64_t)in.tile0 * kBatchRowWords, round, a.sync,
-                                    (uint64_t)wall_clock64(), a.spin_ticks, 0};
-    if (!reduce_rows<C>(rows, in.ntiles, in.kahan_only, s_r)) return false;
+// Phase 0 of one tile: the grey-level range of its voxels as two tagged
+// words (or in LDS, `lmm`, when the phase has a single tile).
+__device__ __forceinline__ void tile_range(const BatchArgs& a, int64_t t, const BatchInst& in, const BatchTile& tl,
+                                           uint32_t round, uint32_t* lmm) {
+    const int tid = threadIdx.x;
+    const uint8_t* xi = a.x + in.base;
+    uint32_t lo = 255u, hi = 0u;
+    const uint4* body = reinterpret_cast<const uint4*>(xi + in.head);
+    for (int64_t c = tl.c0 + tid; c < tl.c1; c += kBlock) {
+        const uint4 w = body[c];
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t v = (words[q] >> (8 * b)) & 0xFFu;
+                lo = min(lo, v);
+                hi = max(hi, v);
+            }
+        }
+    }
+    if (tl.ragged) {
+        const int64_t tail0 = in.head + 16 * in.nbody;
+        const int64_t nr = in.head + (in.n - tail0);
+        if (tid < nr) {
+            const int64_t i = tid < in.head ? (int64_t)tid : tail0 + (tid - in.head);
+            lo = min(lo, (uint32_t)xi[i]);
+            hi = max(hi, (uint32_t)xi[i]);
+        }
+    }
+    block_minmax(lo, hi);
+    if (tid == 0) {
+        if (lmm) {
+            lmm[0] = lo;
+            lmm[1] = hi;
+        } else {
+            store_tagged(a.rows + t * kBatchRowWords, round, lo);
+            store_tagged(a.rows + t * kBatchRowWords + 1, round, hi);
+        }
+    }
+}
+
+// Results (history, record, commit times) are written by whichever block
+// completes a phase, on any XCD, and the same record by several of them: the
+// stores go with agent scope, so that no XCD's L2 keeps an older copy that a
+// later write-back could put over a newer one.
+__device__ __forceinline__ void put_f64(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_i32(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_u64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Commit time of phase q of an instance (wall clock), after its history.
+__device__ __forceinline__ uint64_t* commit_times(const BatchArgs& a, const BatchInst& in) {
+    return reinterpret_cast<uint64_t*>(a.hist + in.hist + (int64_t)(in.max_iter + 2) * (in.C + 2));
+}
+
+// Opens the next phase (tag `round`) of instance i with its tile 0 already
+// taken by the calling block (thread 0), which goes on with it at once.
+__device__ __forceinline__ void open_phase(const BatchArgs& a, int i, uint32_t round) {
+    __hip_atomic_store(a.ctl + i, ((uint64_t)round << 32) | kBatchClaim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    (void)__hip_atomic_fetch_add(&a.sync->epoch, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Completion of phase 0 (block that finished its last tile): reduce the
+// ranges (tagged rows, or `lmm` for a single tile), v^0 into the record and
+// the history, then pass 0 opens with this block on its tile 0 and the
+// decision in `d` (published for the other blocks when the pass has more
+// tiles).  Returns false (all threads) if a wait was abandoned.
+__device__ __forceinline__ bool finish_range(const BatchArgs& a, int i, const BatchInst& in, uint32_t round,
+                                             const uint32_t* lmm, Decision& d) {
+    uint32_t lo, hi;
+    if (lmm) {
+        lo = lmm[0];
+        hi = lmm[1];
+    } else {
+        const uint64_t t0 = wall_clock64();
+        auto get = [&](int b, uint32_t& l, uint32_t& h) {
+            uint32_t raw[2];
+            if (!batch_poll<2>(a.rows + ((int64_t)in.tile0 + b) * kBatchRowWords, round, raw, a.sync, t0,
+                               a.spin_ticks))
+                return false;
+            l = raw[0];
+            h = raw[1];
+            return true;
+        };
+        if (!reduce_minmax(get, in.ntiles, lo, hi)) return false;
+    }
     if (threadIdx.x == 0) {
         double* hv = a.hist + in.hist;
-        double* hd = hv + (int64_t)(in.max_iter + 2) * C;
-        double* hJ = hd + (in.max_iter + 2);
-        double vcur[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) vcur[k] = hv[(int64_t)p * C + k];
-        Step<C> s;
-        decide<C>(s_r, p, vcur, in.eps, in.max_iter, s);
-        BatchRec* rec = a.recs + i;
-        hJ[p] = s.J;
-        hd[p] = s.delta;
-        float vn[C], vo[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            rec->vres[k] = vcur[k];
-            vo[k] = (float)vcur[k];
-            vn[k] = s.done ? vo[k] : (float)s.vnext[k];
-            if (!s.done) hv[(int64_t)(p + 1) * C + k] = s.vnext[k];
+        double v64[kMaxC];
+        start_centroids(in.C, lo, hi, in.given, in.v0, in.dv0, v64);
+        for (int k = 0; k < kMaxC; ++k) {
+            const float v = k < in.C ? (float)v64[k] : 0.f;
+            if (k < in.C) put_f64(hv + k, v64[k]);
+            d.vn[k] = d.vo[k] = v;
+            d.v64[k] = (double)v;
         }
-        rec->iters = p;
-        rec->J = s.J;
-        rec->delta = s.delta;
-        rec->passes = p + 1;
-        rec->status = s.status;
-        rec->done = s.done;
-        if (!s.done) rec->pass = p + 1;
-        write_decision(a.dec + (int64_t)i * kBatchDecWords, round, vn, vo, C, s.done ? p : p + 1, s.done);
-        if (s.done) __hip_atomic_fetch_sub(&a.sync->active, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        d.p = 0;
+        BatchRec* rec = a.recs + i;
+        put_i32(&rec->pass, 0);
+        put_i32(&rec->done, 0);
+        put_i32(&rec->iters, -1);
+        put_i32(&rec->status, FCM_RUNNING);
+        put_i32(&rec->passes, 0);
+        put_i32(&rec->lo, (int32_t)lo);
+        put_i32(&rec->hi, (int32_t)hi);
+        put_f64(&rec->delta, __builtin_nan(""));
+        put_f64(&rec->J, __builtin_nan(""));
+        for (int k = 0; k < kMaxC; ++k) put_f64(&rec->vres[k], (double)d.vn[k]);
+        put_u64(commit_times(a, in), wall_clock64());
     }
     __syncthreads();
+    if (phase_tiles(a, i, 1u) > 1)
+        publish_decision(a.dec + (int64_t)i * kBatchDecWords, round + 1, d.vn, d.vo, d.v64, in.C, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) open_phase(a, i, round + 1);
     return true;
 }
 
-__device__ __forceinline__ void batch_publish_round(BatchSync* sy, uint32_t round) {
-    __hip_atomic_fetch_max(&sy->gen_max, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Completion of pass p (block that finished its last tile): reduce the tile
+// rows in tile order (or the one row in LDS), apply Eq.3 and the stopping
+// rule, record, then retire the instance or open pass p + 1 with this block
+// on its tile 0 and the decision in `d`.  Returns 0 (all threads) if a wait
+// was abandoned, 1 if the instance finished, 2 if pass p + 1 was opened.
+template <int C>
+__device__ __forceinline__ int finish_pass(const BatchArgs& a, int i, const BatchInst& in, int p, uint32_t round,
+                                           const float* lrow, Decision& d) {
+    __shared__ Reduced<C> s_r;
+    __shared__ Step<C> s_s;
+    __shared__ double s_vcur[C];
+    const bool fine = tile_set(a, round - a.round0 - 1u) != 0;
+    if (lrow) {
+        if (!reduce_rows<C>(LocalRows<2 * C + 2>{const_cast<float*>(lrow)}, 1, in.kahan_only, s_r)) return 0;
+    } else {
+        const BatchRows<2 * C + 2> rows{a.rows + (int64_t)(fine ? in.tile0f : in.tile0) * kBatchRowWords, round,
+                                        a.sync, (uint64_t)wall_clock64(), a.spin_ticks, 0};
+        if (!reduce_rows<C>(rows, fine ? in.ntilesf : in.ntiles, in.kahan_only, s_r)) return 0;
+    }
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        double vcur[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            vcur[k] = d.v64[k];
+            s_vcur[k] = vcur[k];
+        }
+        decide<C>(s_r, p, vcur, in.eps, in.max_iter, s_s);
+    }
+    __syncthreads();
+    double* hv = a.hist + in.hist;
+    BatchRec* rec = a.recs + i;
+    const bool done = s_s.done != 0;
+    if (tid < C) {
+        put_f64(&rec->vres[tid], s_vcur[tid]);
+        if (!done) put_f64(hv + (int64_t)(p + 1) * C + tid, s_s.vnext[tid]);
+    } else if (tid == 64) {
+        double* hd = hv + (int64_t)(in.max_iter + 2) * C;
+        double* hJ = hd + (in.max_iter + 2);
+        put_f64(hJ + p, s_s.J);
+        put_f64(hd + p, s_s.delta);
+        put_i32(&rec->iters, p);
+        put_f64(&rec->J, s_s.J);
+        put_f64(&rec->delta, s_s.delta);
+        put_i32(&rec->passes, p + 1);
+        put_i32(&rec->status, s_s.status);
+        put_i32(&rec->done, s_s.done);
+        if (!done) put_i32(&rec->pass, p + 1);
+        put_u64(commit_times(a, in) + p + 1, wall_clock64());
+    }
+    if (done) {
+        if (tid == 0) {
+            __hip_atomic_store(a.ctl + i, ((uint64_t)(round + 1) << 32) | kBatchDoneClaims, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_sub(&a.sync->tiles_left, (uint32_t)max(in.ntiles, in.ntilesf), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_sub(&a.sync->active, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        return 1;
+    }
+    // the decision of pass p + 1: this block's copy, and the other blocks'
+    // tagged words when the pass has more than one tile
+    if (tid < kMaxC) {
+        d.vo[tid] = tid < C ? (float)s_vcur[tid] : 0.f;
+        d.vn[tid] = tid < C ? (float)s_s.vnext[tid] : 0.f;
+        d.v64[tid] = tid < C ? s_s.vnext[tid] : 0.0;
+    }
+    if (tid == 0) d.p = p + 1;
+    __syncthreads();
+    if (phase_tiles(a, i, round + 1u - a.round0 - 1u) > 1)
+        publish_decision(a.dec + (int64_t)i * kBatchDecWords, round + 1, d.vn, d.vo, d.v64, C, p + 1);
+    __syncthreads();
+    if (tid == 0) open_phase(a, i, round + 1);
+    return 2;
+}
+
+// Block-wide choice of an instance with tiles left: every thread inspects the
+// instances at rotation positions tid, tid + kBlock, ... from `start`; the
+// nearest in rotation order wins.  Blocks start their rotations at spread
+// positions, so that free blocks seldom race for the same tile.  Returns the
+// instance or -1 (all threads).
+__device__ __forceinline__ int pick_instance(const BatchArgs& a, int start) {
+    __shared__ int s_pos[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int best = 0x7FFFFFFF;
+    for (int j = tid; j < a.I; j += kBlock) {
+        int i = start + j;
+        if (i >= a.I) i -= a.I;
+        const uint64_t w = __hip_atomic_load(a.ctl + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t phase = (uint32_t)(w >> 32) - a.round0 - 1u;
+        if ((uint32_t)(w & 0xFFFFu) < (uint32_t)phase_tiles(a, i, phase)) {
+            best = j;
+            break;  // later positions of this thread are further away
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) best = min(best, __shfl_xor(best, off, 64));
+    if (lane == 0) s_pos[wid] = best;
+    __syncthreads();
+    best = s_pos[0];
+    for (int w = 1; w < kWaves; ++w) best = min(best, s_pos[w]);
+    __syncthreads();
+    if (best == 0x7FFFFFFF) return -1;
+    const int i = start + best;
+    return i >= a.I ? i - a.I : i;
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void fcm_batch_kernel(BatchArgs a) {
-    const int G = gridDim.x;
+__global__ __launch_bounds__(kBlock, 2) void fcm_batch_kernel(BatchArgs a) {
     const int tid = threadIdx.x;
     BatchSync* sy = a.sync;
-    __shared__ float s_vn[kMaxC], s_vo[kMaxC];
-    __shared__ int s_state, s_p;
-    uint32_t round = a.round0;
-
-    if (a.do_init) {
-        ++round;
-        for (int64_t t = blockIdx.x; t < a.ntiles; t += G) {
-            const BatchTile tl = a.tiles[t];
-            const BatchInst& in = a.inst[tl.inst];
-            const uint8_t* xi = a.x + in.base;
-            uint32_t lo = 255u, hi = 0u;
-            const uint4* body = reinterpret_cast<const uint4*>(xi + in.head);
-            for (int64_t c = tl.c0 + tid; c < tl.c1; c += kBlock) {
-                const uint4 w = body[c];
-                const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const uint32_t v = (words[q] >> (8 * b)) & 0xFFu;
-                        lo = min(lo, v);
-                        hi = max(hi, v);
+    __shared__ Decision s_d;
+    __shared__ float s_row[2 * kMaxC + 2];
+    __shared__ uint32_t s_mm[2];
+    __shared__ int s_inst, s_k, s_last, s_go, s_ok;
+    __shared__ uint32_t s_tag;
+    if (blockIdx.x == 0 && tid == 0) sy->t_start = wall_clock64();
+    const int start = (int)(((uint64_t)blockIdx.x * (uint32_t)a.I) / gridDim.x);
+    uint64_t idle0 = wall_clock64();
+    int spins = 0;
+    int cur = -1;      // the instance of this block's last tile: tried first
+    uint32_t seen = 0xFFFFFFFFu;  // epoch before this block's last scan that found nothing (thread 0)
+    uint32_t ep = 0;              // epoch read at the top of this round (thread 0)
+    bool have = false; // the block holds its next tile (tile 0 of a phase it opened, or the next open
+                       // tile of the phase it works on) and that phase's decision
+    int inst = -1, k = 0;
+    uint32_t tag = 0;
+    while (true) {
+        // Shared values are copied to registers between two barriers before
+        // thread 0 writes them again, so no wave can see a later value.
+        __syncthreads();
+        if (!have) {
+            if (tid == 0) {
+                const uint32_t active = __hip_atomic_load(&sy->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t left = __hip_atomic_load(&sy->tiles_left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t ab = __hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ep = __hip_atomic_load(&sy->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_go = active != 0u && ab == 0u && blockIdx.x < left;
+                // stay with the last instance while it has tiles open: no
+                // scan, and the blocks that share an instance stay together;
+                // after a scan that found nothing, scan again only once a
+                // phase has opened since (-3: nothing new)
+                s_inst = ep == seen ? -3 : -2;
+                if (cur >= 0) {
+                    const uint64_t w = __hip_atomic_load(a.ctl + cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t phase = (uint32_t)(w >> 32) - a.round0 - 1u;
+                    if ((uint32_t)(w & 0xFFFFu) < (uint32_t)phase_tiles(a, cur, phase)) s_inst = cur;
+                }
+            }
+            __syncthreads();
+            const int go = s_go, sticky = s_inst;
+            __syncthreads();
+            if (!go) break;
+            const int i = sticky >= 0 ? sticky : (sticky == -3 ? -1 : pick_instance(a, start));
+            if (tid == 0) {
+                s_inst = -1;
+                if (i >= 0) {
+                    const uint64_t old = __hip_atomic_fetch_add(a.ctl + i, kBatchClaim, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t kk = (uint32_t)(old & 0xFFFFu);
+                    const uint32_t phase = (uint32_t)(old >> 32) - a.round0 - 1u;
+                    if (kk < (uint32_t)phase_tiles(a, i, phase)) {
+                        s_inst = i;
+                        s_k = (int)kk;
+                        s_tag = (uint32_t)(old >> 32);
                     }
                 }
             }
-            if (tl.ragged) {
-                const int64_t tail0 = in.head + 16 * in.nbody;
-                const int64_t nr = in.head + (in.n - tail0);
-                if (tid < nr) {
-                    const int64_t i = tid < in.head ? (int64_t)tid : tail0 + (tid - in.head);
-                    lo = min(lo, (uint32_t)xi[i]);
-                    hi = max(hi, (uint32_t)xi[i]);
-                }
-            }
-            block_minmax(lo, hi);
-            if (tid == 0) {
-                store_tagged(a.mm + 2 * t, round, lo);
-                store_tagged(a.mm + 2 * t + 1, round, hi);
-            }
             __syncthreads();
-        }
-        for (int i = blockIdx.x; i < a.I; i += G) {
-            const BatchInst& in = a.inst[i];
-            const uint64_t t0 = wall_clock64();
-            auto get = [&](int b, uint32_t& l, uint32_t& h) {
-                uint32_t raw[2];
-                if (!batch_poll<2>(a.mm + 2 * ((int64_t)in.tile0 + b), round, raw, sy, t0, a.spin_ticks)) return false;
-                l = raw[0];
-                h = raw[1];
-                return true;
-            };
-            uint32_t lo, hi;
-            if (!reduce_minmax(get, in.ntiles, lo, hi)) return;
-            if (tid == 0) {
-                double* hv = a.hist + in.hist;
-                float v[kMaxC];
-                double v64[kMaxC];
-                start_centroids(in.C, lo, hi, in.given, in.v0, in.dv0, v64);
-                for (int k = 0; k < kMaxC; ++k) {
-                    v[k] = 0.f;
-                    if (k < in.C) {
-                        hv[k] = v64[k];
-                        v[k] = (float)v64[k];
+            inst = s_inst;
+            k = s_k;
+            tag = s_tag;
+            if (inst < 0) {
+                // nothing to take right now (every open tile is being run, or
+                // the instances are between phases): back off, bounded by the
+                // wait limit; a lost race for a tile retries at once
+                if (tid == 0) {
+                    // the epoch was read before the scan, so a phase opened
+                    // during the scan makes the next round scan again
+                    if (i < 0 && sticky != -3) seen = ep;
+                    if (wall_clock64() - idle0 > a.spin_ticks) {
+                        // the next round reads the abort word and leaves
+                        __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else if (i < 0) {
+                        ++spins;
+                        if (spins < 8)
+                            __builtin_amdgcn_s_sleep(2);
+                        else if (spins < 64)
+                            __builtin_amdgcn_s_sleep(8);
+                        else
+                            __builtin_amdgcn_s_sleep(32);
                     }
                 }
-                BatchRec* rec = a.recs + i;
-                rec->pass = 0;
-                rec->done = 0;
-                rec->iters = -1;
-                rec->status = FCM_RUNNING;
-                rec->passes = 0;
-                rec->lo = (int32_t)lo;
-                rec->hi = (int32_t)hi;
-                rec->delta = __builtin_nan("");
-                rec->J = __builtin_nan("");
-                for (int k = 0; k < kMaxC; ++k) rec->vres[k] = (double)v[k];
-                write_decision(a.dec + (int64_t)i * kBatchDecWords, round, v, v, in.C, 0, 0);
+                continue;
             }
-            __syncthreads();
+            if (tag - a.round0 - 1u >= 1u) {
+                // the decision of the pass (and v^p in FP64 for completing it)
+                if (tid == 0) {
+                    uint32_t raw[kBatchDecWords];
+                    s_ok = batch_poll<kBatchDecWords>(a.dec + (int64_t)inst * kBatchDecWords, tag, raw, sy,
+                                                      wall_clock64(), a.spin_ticks);
+                    for (int q = 0; q < kMaxC; ++q) {
+                        const uint64_t bits =
+                            (uint64_t)raw[kBatchDecF64 + 2 * q] | ((uint64_t)raw[kBatchDecF64 + 2 * q + 1] << 32);
+                        s_d.vn[q] = __builtin_bit_cast(float, raw[q]);
+                        s_d.vo[q] = __builtin_bit_cast(float, raw[kMaxC + q]);
+                        s_d.v64[q] = __builtin_bit_cast(double, bits);
+                    }
+                    s_d.p = (int)raw[2 * kMaxC];
+                }
+                __syncthreads();
+                if (!s_ok) break;
+            }
         }
-    }
-
-    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
-        if (__hip_atomic_load(&sy->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) break;
-        const uint32_t rd = round, rw = round + 1;
-        for (int64_t t = blockIdx.x; t < a.ntiles; t += G) {
-            const BatchTile tl = a.tiles[t];
-            const BatchInst& in = a.inst[tl.inst];
+        have = false;
+        spins = 0;
+        cur = inst;
+        const BatchInst& in = a.inst[inst];
+        const uint32_t phase = tag - a.round0 - 1u;
+        const int fine = tile_set(a, phase);
+        const int ntiles = fine ? in.ntilesf : in.ntiles;
+        const bool local = ntiles == 1;
+        const int64_t t = (int64_t)(fine ? in.tile0f : in.tile0) + k;
+        const BatchTile tl = a.tiles[t];
+        if (phase == 0u) {
+            tile_range(a, t, in, tl, tag, local ? s_mm : nullptr);
+        } else {
+            float* lrow = local ? s_row : nullptr;
+            switch (in.C) {
+                case 2: tile_pass<2>(a, t, in, tl, s_d, tag, lrow); break;
+                case 3: tile_pass<3>(a, t, in, tl, s_d, tag, lrow); break;
+                case 4: tile_pass<4>(a, t, in, tl, s_d, tag, lrow); break;
+                case 5: tile_pass<5>(a, t, in, tl, s_d, tag, lrow); break;
+                case 6: tile_pass<6>(a, t, in, tl, s_d, tag, lrow); break;
+                case 7: tile_pass<7>(a, t, in, tl, s_d, tag, lrow); break;
+                default: tile_pass<8>(a, t, in, tl, s_d, tag, lrow); break;
+            }
+        }
+        __syncthreads();  // the row is written (issued) before the arrival
+        bool last = true;
+        if (!local) {
+            // one atomic add marks this tile finished and takes the next open
+            // tile of the same phase, whose decision this block already holds
             if (tid == 0) {
-                float vn[kMaxC], vo[kMaxC];
-                int p = 0;
-                s_state = read_decision(a.dec + (int64_t)tl.inst * kBatchDecWords, rd, a.round0 + 1u, sy, a.spin_ticks,
-                                        vn, vo, p);
-                for (int k = 0; k < kMaxC; ++k) {
-                    s_vn[k] = vn[k];
-                    s_vo[k] = vo[k];
-                }
-                s_p = p;
+                const uint64_t old = __hip_atomic_fetch_add(a.ctl + inst, kBatchArrive | kBatchClaim,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_last = (int)((old >> 16) & 0xFFFFu) == ntiles - 1;
+                s_k = (int)(old & 0xFFFFu);
             }
             __syncthreads();
-            const int state = s_state;
-            if (state < 0) return;
-            if (state > 0) {
-                switch (in.C) {
-                    case 2: tile_pass<2>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    case 3: tile_pass<3>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    case 4: tile_pass<4>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    case 5: tile_pass<5>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    case 6: tile_pass<6>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    case 7: tile_pass<7>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                    default: tile_pass<8>(a, t, in, tl, s_p, s_vn, s_vo, rw); break;
-                }
+            last = s_last != 0;
+            const int next = s_k;
+            if (!last && next < ntiles) {
+                have = true;
+                k = next;
+                idle0 = wall_clock64();
+                continue;
             }
-            __syncthreads();
         }
-        for (int i = blockIdx.x; i < a.I; i += G) {
-            const BatchInst& in = a.inst[i];
-            if (tid == 0) {
-                s_state = a.recs[i].done;
-                s_p = a.recs[i].pass;
-            }
-            __syncthreads();
-            if (!s_state) {
-                bool ok;
+        if (last) {
+            int r;
+            if (phase == 0u) {
+                r = finish_range(a, inst, in, tag, local ? s_mm : nullptr, s_d) ? 2 : 0;
+            } else {
+                const int p = (int)phase - 1;
+                const float* lrow = local ? s_row : nullptr;
                 switch (in.C) {
-                    case 2: ok = owner_step<2>(a, i, in, s_p, rw); break;
-                    case 3: ok = owner_step<3>(a, i, in, s_p, rw); break;
-                    case 4: ok = owner_step<4>(a, i, in, s_p, rw); break;
-                    case 5: ok = owner_step<5>(a, i, in, s_p, rw); break;
-                    case 6: ok = owner_step<6>(a, i, in, s_p, rw); break;
-                    case 7: ok = owner_step<7>(a, i, in, s_p, rw); break;
-                    default: ok = owner_step<8>(a, i, in, s_p, rw); break;
+                    case 2: r = finish_pass<2>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 3: r = finish_pass<3>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 4: r = finish_pass<4>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 5: r = finish_pass<5>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 6: r = finish_pass<6>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 7: r = finish_pass<7>(a, inst, in, p, tag, lrow, s_d); break;
+                    default: r = finish_pass<8>(a, inst, in, p, tag, lrow, s_d); break;
                 }
-                if (!ok) return;
             }
-            __syncthreads();
+            if (r == 0) break;
+            if (r == 2) {  // go on with tile 0 of the phase just opened
+                have = true;
+                k = 0;
+                tag = tag + 1u;
+            }
         }
-        round = rw;
+        idle0 = wall_clock64();
     }
-    if (tid == 0) batch_publish_round(sy, round);
 }
 
 // Labels of every instance: per tile, the 256-entry nearest-centroid table of
@@ -476,10 +731,8 @@ hipError_t batch_max_grid(int ncu, int* max_grid) {
 }
 
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s) {
-    BatchArgs copy = a;
-    void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fcm_batch_kernel), dim3(grid), dim3(kBlock), args,
-                                      0, s);
+    hipLaunchKernelGGL(fcm_batch_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s) {

@@ -316,13 +316,9 @@ struct TaggedRows {
     uint32_t round;
     SyncState* sy;
     uint64_t t0, limit;
-    bool local;  // two-level exchange: the row is read only on this XCD, so it goes to its L2
+    bool two_level;  // read only by the block's XCD leader (the stores are agent-scope either way)
     __device__ __forceinline__ void put(int q, uint32_t payload) const {
-        uint64_t* p = W + (size_t)blockIdx.x * S + q;
-        if (local)
-            __hip_atomic_store(p, tagged(round, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            store_tagged(p, round, payload);
+        store_tagged(W + (size_t)blockIdx.x * S + q, round, payload);
     }
     __device__ __forceinline__ void put_pair(int q, float s, float c) const {
         put(q, __builtin_bit_cast(uint32_t, s - c));
@@ -807,10 +803,11 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
 }
 
 // Two-level exchange of a persistent launch (each block's row already
-// stored to its XCD's L2).  Level 1: block x < kXcds polls the rows of blocks
-// x, x + kXcds, ... (which share its XCD; one row per thread, agent-scope
-// loads served by that L2), adds them in FP64 in that order (wave butterflies,
-// then the waves in order) and stores its XCD row with agent scope.  Level 2:
+// stored, with agent scope like every exchange word).  Level 1: block
+// x < kXcds polls the rows of blocks x, x + kXcds, ... (which share its XCD
+// when the blocks were dealt to the XCDs in turn; one row per thread),
+// adds them in FP64 in that order (wave butterflies, then the waves in
+// order) and stores its XCD row.  Level 2:
 // every block polls the (up to) kXcds XCD rows and adds them in XCD order, so
 // all blocks hold bitwise identical sums and take the decision themselves.
 // False in every thread if a wait hit its time limit.
@@ -1365,8 +1362,8 @@ __global__ __launch_bounds__(kBlock) void fcm_persist_kernel(PassArgs a) {
         ++round;
         constexpr int K = 2 * C + 2;
         const bool two_level = s_xcd != 0;
-        const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * TaggedRows<K>::S * G, round, sy, (uint64_t)wall_clock64(),
-                                 a.spin_ticks, two_level};
+        const TaggedRows<K> rows{a.rows + (size_t)(round & 1u) * TaggedRows<K>::S * G, round, sy,
+                                 (uint64_t)wall_clock64(), a.spin_ticks, two_level};
         write_partial_row<C>(acc, rows);
         if (leader || a.allgather || two_level) {
             // every block of an all-gather or two-level launch reduces the

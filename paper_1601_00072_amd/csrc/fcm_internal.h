@@ -126,17 +126,42 @@ struct LabelArgs {
     int32_t bytewise;      // x and labels differ in 16-byte alignment
 };
 
-// ---- batched solver: many instances of uneven size in one cooperative launch ----
+// ---- batched solver: many instances of uneven size in one persistent launch ----
 
 constexpr int kBatchRowWords = 32;  // stride of a tile row (2C + 2 tagged words used), 256-byte aligned
-constexpr int kBatchDecWords = 2 * kMaxC + 1;  // tagged decision words per instance
+// Tagged decision words per instance: v^p (FP32) [kMaxC], v^(p-1) (FP32)
+// [kMaxC], p, then v^p in FP64 as two halves each [2 kMaxC].  The block that
+// completes the next pass takes v^p from here, not from the history: it may
+// run on another XCD, whose L2 need not hold the history's latest contents.
+constexpr int kBatchDecWords = 4 * kMaxC + 1;
+constexpr int kBatchDecF64 = 2 * kMaxC + 1;  // offset of the FP64 halves
+
+// Control word of an instance (64 bits, changed only by agent-scope atomics):
+//   bits 63..32  tag of the instance's current phase (phase 0: data range,
+//                phase p + 1: fused pass p), round0 + 1 + phase
+//   bits 31..16  tiles of the phase whose rows are written (arrivals)
+//   bits 15..0   tiles of the phase handed out (claims)
+// A finished instance keeps claims at kBatchDoneClaims, above any tile count.
+constexpr uint64_t kBatchClaim = 1ull;
+constexpr uint64_t kBatchArrive = 1ull << 16;
+constexpr uint32_t kBatchDoneClaims = 0x8000u;
+constexpr int32_t kBatchFineFrom = 48;      // default first pass on the fine tiles
+constexpr int32_t kBatchFineChunks = 2;     // default chunks per thread of a fine tile
+constexpr int32_t kBatchChunks = 8;         // default chunks per thread of a coarse tile
+constexpr int32_t kBatchMaxTiles = 0x6000;  // tiles per instance: a phase's claims stay below 2^16 (every
+                                            // arrival also claims, so at most twice the tiles plus one
+                                            // per concurrent claimer, kMaxPersistGrid)
 
 struct BatchInst {
     int64_t base;        // byte offset of the instance's first voxel in the input
     int64_t n, head, nbody;
-    int64_t hist;        // offset (doubles) of its history: v (max_iter + 2) * C, delta, J (max_iter + 2 each)
+    int64_t hist;        // offset (doubles) of its history: v (max_iter + 2) * C, then delta, J and the
+                         // commit times (max_iter + 2 each)
     int32_t C, mclass, max_iter, kahan_only;
-    int32_t given, tile0, ntiles, pad;   // given: start mode (0 spaced, 1 v0, 2 dv0)
+    int32_t given;       // start mode (0 spaced, 1 v0, 2 dv0)
+    int32_t tile0, ntiles;    // coarse tiles: phase 0 and passes below BatchArgs::fine_from
+    int32_t tile0f, ntilesf;  // fine tiles (one chunk per thread): the later passes
+    int32_t pad;
     float alpha, mexp;
     double eps;
     double v0[kMaxC];
@@ -149,32 +174,35 @@ struct BatchTile {
     int32_t ragged;      // this tile also takes the instance's unaligned head and tail voxels
 };
 
-struct BatchRec {        // per-instance state, written by the instance's owner block
+struct BatchRec {        // per-instance result, written by the block that completes each phase
     int32_t pass, done, iters, status, passes, lo, hi, pad;
     double delta, J;
     double vres[kMaxC];
 };
 
 struct BatchSync {
-    uint32_t gen_max;    // largest round used by any block (for the next launch's tags)
     uint32_t abort;      // set when a wait hit its time limit; every block then exits
     uint32_t active;     // instances not yet finished
-    uint32_t pad;
+    uint32_t tiles_left; // tiles of the instances not yet finished
+    uint32_t epoch;      // phases opened so far: blocks without work rescan only when it changes
+    uint64_t t_start;    // wall clock at the start of the launch (block 0)
 };
 
 struct BatchArgs {
     const uint8_t* x;
     const BatchInst* inst;
+    const int32_t* ntiles;  // [I][2] coarse and fine tiles per instance (dense copy for the scan)
     const BatchTile* tiles;
     BatchRec* recs;
     double* hist;
-    uint64_t* rows;      // [ntiles][kBatchRowWords] tagged tile rows
-    uint64_t* mm;        // [ntiles][2] tagged grey-level ranges
-    uint64_t* dec;       // [I][kBatchDecWords] tagged decisions: v_new[8], v_old[8], (pass << 1 | done)
+    uint64_t* rows;      // [ntiles][kBatchRowWords] tagged tile rows (phase 0: grey-level range)
+    uint64_t* dec;       // [I][kBatchDecWords] tagged decisions (see kBatchDecWords)
+    uint64_t* ctl;       // [I] control words, round0 + 1 << 32 at launch
     BatchSync* sync;
-    int32_t I, ntiles, do_init, max_sweeps;
-    uint32_t round0;     // largest round of earlier launches
-    uint32_t pad;
+    int32_t I;
+    int32_t fine_from;   // passes from this one on run on the fine tiles
+    uint32_t round0;     // tags of this launch are above round0
+    uint32_t pad2;
     uint64_t spin_ticks;
 };
 

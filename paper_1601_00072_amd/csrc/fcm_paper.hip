@@ -31,18 +31,26 @@ __global__ __launch_bounds__(kPaperPixelBlock) void paper_terms_kernel(const flo
     den[i] = a;
 }
 
-// Algorithm 2: block b sums A[2 b B .. 2 b B + 2 B) (zero past n) into B[b]
+// The reduction structure of Algorithm 2 (Sec. 4.2): blocks of 128 threads,
+// each thread first adds its two inputs -- elements t and t + 128 of the
+// block's 256-element window, zero past n -- in a register, then the block
+// halves its 128 sums in shared memory level by level (a barrier before
+// every level) and stores one partial sum per block.
 __global__ __launch_bounds__(kPaperReduceBlock) void paper_reduce_kernel(const float* A, int64_t n, float* Bout) {
-    __shared__ float part[2 * kPaperReduceBlock];
+    __shared__ float acc[kPaperReduceBlock];
     const int t = threadIdx.x;
-    const int64_t start = 2 * (int64_t)blockIdx.x * kPaperReduceBlock;
-    part[t] = start + t < n ? A[start + t] : 0.0f;
-    part[t + kPaperReduceBlock] = start + t + kPaperReduceBlock < n ? A[start + t + kPaperReduceBlock] : 0.0f;
-    for (int stride = kPaperReduceBlock; stride > 0; stride /= 2) {
-        __syncthreads();
-        if (t < stride) part[t] += part[t + stride];
+    const int64_t window = (int64_t)blockIdx.x * (2 * kPaperReduceBlock);
+    float s = 0.0f;
+    for (int q = 0; q < 2; ++q) {
+        const int64_t i = window + q * kPaperReduceBlock + t;
+        if (i < n) s += A[i];
     }
-    if (t == 0) Bout[blockIdx.x] = part[0];
+    acc[t] = s;
+    for (int width = kPaperReduceBlock / 2; width >= 1; width >>= 1) {
+        __syncthreads();
+        if (t < width) acc[t] += acc[t + width];
+    }
+    if (t == 0) Bout[blockIdx.x] = acc[0];
 }
 
 // one thread: the final sums of both reductions and the centroid of cluster j

@@ -885,9 +885,13 @@ struct fcm_batch {
     std::vector<const double*> own_dv0;  // FCM_INIT_DEVICE start arrays of the caller
     hipStream_t stream = nullptr;
     int device = 0, ncu = 256, max_grid = 1, grid = 1, grid_req = 0;
-    int chunks_per_thread = 4;
+    int chunks_per_thread = kBatchChunks;
+    int fine_from = kBatchFineFrom;   // passes from this one on use the fine tiles
+    int fine_chunks = kBatchFineChunks;  // chunks per thread of a fine tile
+    int64_t coarse_tiles = 0;         // tiles of the coarse set (the first in the table)
     uint64_t spin_ticks = 0;
-    uint32_t round = 0;        // largest round used so far (tags of later solves start above it)
+    double clock_mhz = 100.0;  // wall clock of the device
+    uint32_t round = 0;        // largest tag used so far (tags of later solves start above it)
     bool solved = false;
 
     std::vector<BatchInst> h_inst;
@@ -895,16 +899,18 @@ struct fcm_batch {
     int64_t hist_total = 0;
 
     BatchInst* d_inst = nullptr;
+    int32_t* d_ntiles = nullptr;
     BatchTile* d_tiles = nullptr;
     BatchRec* d_recs = nullptr;
     double* d_hist = nullptr;
     uint64_t* d_rows = nullptr;
-    uint64_t* d_mm = nullptr;
     uint64_t* d_dec = nullptr;
+    uint64_t* d_ctl = nullptr;
     BatchSync* d_sync = nullptr;
-    int64_t tiles_cap = 0;     // capacity of d_tiles / d_rows / d_mm
+    int64_t tiles_cap = 0;     // capacity of d_tiles / d_rows
     BatchRec* h_recs = nullptr;
     BatchSync* h_sync = nullptr;
+    uint64_t* h_ctl = nullptr;
 
     // learned starts (first fcm_batch_set_start with a network)
     int64_t* d_off = nullptr;      // offsets [count + 1]
@@ -919,48 +925,57 @@ namespace {
 void batch_free_tiles(fcm_batch* b) {
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_rows) (void)hipFree(b->d_rows);
-    if (b->d_mm) (void)hipFree(b->d_mm);
     b->d_tiles = nullptr;
     b->d_rows = nullptr;
-    b->d_mm = nullptr;
     b->tiles_cap = 0;
 }
 
 void batch_release(fcm_batch* b) {
     if (!b) return;
     batch_free_tiles(b);
-    if (b->d_inst) (void)hipFree(b->d_inst);
-    if (b->d_recs) (void)hipFree(b->d_recs);
-    if (b->d_hist) (void)hipFree(b->d_hist);
-    if (b->d_dec) (void)hipFree(b->d_dec);
-    if (b->d_sync) (void)hipFree(b->d_sync);
+    for (void* p : {(void*)b->d_inst, (void*)b->d_ntiles, (void*)b->d_recs, (void*)b->d_hist, (void*)b->d_dec,
+                    (void*)b->d_ctl, (void*)b->d_sync, (void*)b->d_off, (void*)b->d_counts, (void*)b->d_whist,
+                    (void*)b->d_wy, (void*)b->d_wv0})
+        if (p) (void)hipFree(p);
     if (b->h_recs) (void)hipHostFree(b->h_recs);
     if (b->h_sync) (void)hipHostFree(b->h_sync);
-    for (void* p : {(void*)b->d_off, (void*)b->d_counts, (void*)b->d_whist, (void*)b->d_wy, (void*)b->d_wv0})
-        if (p) (void)hipFree(p);
+    if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     delete b;
 }
 
-// Cut every instance into tiles of 256 * chunks_per_thread chunks and upload
-// the instance and tile tables (the tile-indexed buffers grow as needed and
-// are cleared, so no stale tag can match).
+// Cut every instance into two tile sets -- coarse tiles of 256 *
+// chunks_per_thread chunks (phase 0 and the early passes), then fine tiles of
+// 256 * fine_chunks chunks (the later passes); more chunks per tile where an
+// instance would need more than kBatchMaxTiles tiles -- and upload the
+// instance and tile tables (the coarse tiles of every instance first).  The
+// tile-indexed buffers grow as needed and are cleared, so no stale tag can
+// match.
 int batch_build_tiles(fcm_batch* b) {
-    const int64_t tile_chunks = (int64_t)kBlock * b->chunks_per_thread;
     b->h_tiles.clear();
-    for (int32_t i = 0; i < b->count; ++i) {
-        BatchInst& in = b->h_inst[i];
-        in.tile0 = (int32_t)b->h_tiles.size();
-        int64_t c0 = 0;
-        do {
-            BatchTile t{};
-            t.c0 = c0;
-            t.c1 = std::min<int64_t>(in.nbody, c0 + tile_chunks);
-            t.inst = i;
-            t.ragged = c0 == 0 ? 1 : 0;
-            b->h_tiles.push_back(t);
-            c0 = t.c1;
-        } while (c0 < in.nbody);
-        in.ntiles = (int32_t)b->h_tiles.size() - in.tile0;
+    std::vector<int32_t> nt_of((size_t)b->count * 2);
+    for (int set = 0; set < 2; ++set) {
+        const int cpt = set ? b->fine_chunks : b->chunks_per_thread;
+        for (int32_t i = 0; i < b->count; ++i) {
+            BatchInst& in = b->h_inst[i];
+            const int64_t tile_chunks =
+                std::max<int64_t>((int64_t)kBlock * cpt, (in.nbody + kBatchMaxTiles - 1) / kBatchMaxTiles);
+            const int32_t first = (int32_t)b->h_tiles.size();
+            int64_t c0 = 0;
+            do {
+                BatchTile t{};
+                t.c0 = c0;
+                t.c1 = std::min<int64_t>(in.nbody, c0 + tile_chunks);
+                t.inst = i;
+                t.ragged = c0 == 0 ? 1 : 0;
+                b->h_tiles.push_back(t);
+                c0 = t.c1;
+            } while (c0 < in.nbody);
+            const int32_t count = (int32_t)b->h_tiles.size() - first;
+            (set ? in.tile0f : in.tile0) = first;
+            (set ? in.ntilesf : in.ntiles) = count;
+            nt_of[(size_t)i * 2 + set] = count;
+        }
+        if (!set) b->coarse_tiles = (int64_t)b->h_tiles.size();
     }
     const int64_t nt = (int64_t)b->h_tiles.size();
     if (nt > (int64_t)INT32_MAX) return FCM_EINVAL;
@@ -968,17 +983,20 @@ int batch_build_tiles(fcm_batch* b) {
         batch_free_tiles(b);
         if (hipMalloc(&b->d_tiles, sizeof(BatchTile) * nt) != hipSuccess) return FCM_ENOMEM;
         if (hipMalloc(&b->d_rows, sizeof(uint64_t) * kBatchRowWords * nt) != hipSuccess) return FCM_ENOMEM;
-        if (hipMalloc(&b->d_mm, sizeof(uint64_t) * 2 * nt) != hipSuccess) return FCM_ENOMEM;
         b->tiles_cap = nt;
     }
     FCM_HIP(hipMemsetAsync(b->d_rows, 0, sizeof(uint64_t) * kBatchRowWords * b->tiles_cap, b->stream));
-    FCM_HIP(hipMemsetAsync(b->d_mm, 0, sizeof(uint64_t) * 2 * b->tiles_cap, b->stream));
+    FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
     FCM_HIP(hipMemcpyAsync(b->d_tiles, b->h_tiles.data(), sizeof(BatchTile) * nt, hipMemcpyHostToDevice, b->stream));
     FCM_HIP(hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice,
                            b->stream));
+    FCM_HIP(hipMemcpyAsync(b->d_ntiles, nt_of.data(), sizeof(int32_t) * 2 * b->count, hipMemcpyHostToDevice,
+                           b->stream));
     FCM_HIP(hipStreamSynchronize(b->stream));  // the host tables may change after return
+    int64_t most = 0;
+    for (const BatchInst& in : b->h_inst) most += std::max(in.ntiles, in.ntilesf);
     const int64_t want = b->grid_req > 0 ? b->grid_req : b->max_grid;
-    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, b->max_grid), nt));
+    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, b->max_grid), most));
     b->round = 0;  // buffers were cleared: tags restart
     return FCM_OK;
 }
@@ -1025,7 +1043,7 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
         in.head = std::min<int64_t>(in.n, (int64_t)((16 - (addr & 15)) & 15));
         in.nbody = (in.n - in.head) / 16;
         in.hist = hist;
-        hist += (int64_t)(q.max_iter + 2) * (q.n_clusters + 2);
+        hist += (int64_t)(q.max_iter + 2) * (q.n_clusters + 3);  // v, delta, J, commit times
         in.C = q.n_clusters;
         in.mclass = (q.m == 2.0) ? kM2 : (q.m == 1.5 ? kM15 : kMGeneric);
         in.max_iter = q.max_iter;
@@ -1043,26 +1061,26 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
     if ((e = hipGetDevice(&b->device)) != hipSuccess) return fail(dev_err(e, "hipGetDevice"));
     if ((e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess)
         return fail(dev_err(e, "hipDeviceGetAttribute"));
-    int coop = 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device) != hipSuccess || !coop)
-        return fail(FCM_EUNSUPPORTED);
     int clock_khz = 0;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || clock_khz <= 0)
         clock_khz = 100000;
+    b->clock_mhz = clock_khz / 1000.0;
     b->spin_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
     if ((e = batch_max_grid(b->ncu, &b->max_grid)) != hipSuccess) return fail(dev_err(e, "occupancy"));
     b->max_grid = std::max(1, std::min(b->max_grid, kMaxPersistGrid));
 
     if (hipMalloc(&b->d_inst, sizeof(BatchInst) * count) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_ntiles, sizeof(int32_t) * 2 * count) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipMalloc(&b->d_recs, sizeof(BatchRec) * count) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipMalloc(&b->d_hist, sizeof(double) * hist) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipMalloc(&b->d_dec, sizeof(uint64_t) * kBatchDecWords * count) != hipSuccess) return fail(FCM_ENOMEM);
+    if (hipMalloc(&b->d_ctl, sizeof(uint64_t) * count) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipMalloc(&b->d_sync, sizeof(BatchSync)) != hipSuccess) return fail(FCM_ENOMEM);
     if (hipHostMalloc(&b->h_recs, sizeof(BatchRec) * count, hipHostMallocDefault) != hipSuccess)
         return fail(FCM_ENOMEM);
     if (hipHostMalloc(&b->h_sync, sizeof(BatchSync), hipHostMallocDefault) != hipSuccess) return fail(FCM_ENOMEM);
-    if ((e = hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * count, b->stream)) != hipSuccess)
-        return fail(dev_err(e, "hipMemsetAsync"));
+    if (hipHostMalloc(&b->h_ctl, sizeof(uint64_t) * count, hipHostMallocDefault) != hipSuccess)
+        return fail(FCM_ENOMEM);
     if ((e = hipMemsetAsync(b->d_recs, 0, sizeof(BatchRec) * count, b->stream)) != hipSuccess)
         return fail(dev_err(e, "hipMemsetAsync"));
     int rc = batch_build_tiles(b);
@@ -1077,7 +1095,14 @@ int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid) 
     b->chunks_per_thread = chunks_per_thread;
     b->grid_req = grid;
     b->solved = false;
-    FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
+    return batch_build_tiles(b);
+}
+
+int fcm_batch_set_tail_tiling(fcm_batch* b, int32_t from_pass, int32_t chunks_per_thread) {
+    if (!b || from_pass < 0 || chunks_per_thread < 1 || chunks_per_thread > 64) return FCM_EINVAL;
+    b->fine_from = from_pass;
+    b->fine_chunks = chunks_per_thread;
+    b->solved = false;
     return batch_build_tiles(b);
 }
 
@@ -1125,40 +1150,51 @@ int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
     if (!b || !out) return FCM_EINVAL;
     int max_iter = 1;
     for (const fcm_params& q : b->p) max_iter = std::max(max_iter, q.max_iter);
-    b->h_sync->gen_max = b->round;
+    // tags of this launch: round0 + 1 + phase, phases 0 .. max_iter + 1, and
+    // the finished mark one above; restart (clearing every tagged word) before
+    // they could wrap
+    if ((uint64_t)b->round + (uint64_t)max_iter + 4 >= 0xFFFF0000ull) {
+        int rc = batch_build_tiles(b);
+        if (rc != FCM_OK) return rc;
+    }
+    const uint32_t round0 = b->round;
+    for (int32_t i = 0; i < b->count; ++i) b->h_ctl[i] = (uint64_t)(round0 + 1u) << 32;
+    int64_t tiles = 0;
+    for (const BatchInst& in : b->h_inst) tiles += std::max(in.ntiles, in.ntilesf);
     b->h_sync->abort = 0;
     b->h_sync->active = (uint32_t)b->count;
-    b->h_sync->pad = 0;
+    b->h_sync->tiles_left = (uint32_t)tiles;
+    b->h_sync->epoch = 0;
+    b->h_sync->t_start = 0;
+    FCM_HIP(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(uint64_t) * b->count, hipMemcpyHostToDevice, b->stream));
     FCM_HIP(hipMemcpyAsync(b->d_sync, b->h_sync, sizeof(BatchSync), hipMemcpyHostToDevice, b->stream));
     BatchArgs a{};
     a.x = b->d_x;
     a.inst = b->d_inst;
+    a.ntiles = b->d_ntiles;
     a.tiles = b->d_tiles;
     a.recs = b->d_recs;
     a.hist = b->d_hist;
     a.rows = b->d_rows;
-    a.mm = b->d_mm;
     a.dec = b->d_dec;
+    a.ctl = b->d_ctl;
     a.sync = b->d_sync;
     a.I = b->count;
-    a.ntiles = (int32_t)b->h_tiles.size();
-    a.do_init = 1;
-    a.max_sweeps = max_iter + 2;
-    a.round0 = b->round;
+    a.fine_from = b->fine_from;
+    a.round0 = round0;
     a.spin_ticks = b->spin_ticks;
     hipError_t e = launch_batch(a, b->grid, b->stream);
-    if (e != hipSuccess) return dev_err(e, "hipLaunchCooperativeKernel (batch)");
+    if (e != hipSuccess) return dev_err(e, "launch (batch)");
     FCM_HIP(hipMemcpyAsync(b->h_recs, b->d_recs, sizeof(BatchRec) * b->count, hipMemcpyDeviceToHost, b->stream));
     FCM_HIP(hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, b->stream));
     FCM_HIP(hipStreamSynchronize(b->stream));
-    if (b->h_sync->abort) {
-        last_error() = "a cross-block wait of the batched solve exceeded its time limit";
+    if (b->h_sync->abort || b->h_sync->active != 0u) {
+        last_error() = "a wait of the batched solve exceeded its time limit";
         // clear every tagged buffer so that the next solve starts clean
-        FCM_HIP(hipMemsetAsync(b->d_dec, 0, sizeof(uint64_t) * kBatchDecWords * b->count, b->stream));
         int rc = batch_build_tiles(b);
         return rc != FCM_OK ? rc : FCM_EDEVICE;
     }
-    b->round = b->h_sync->gen_max;
+    b->round = round0 + (uint32_t)max_iter + 3u;
     b->solved = true;
     int worst = FCM_OK;
     for (int32_t i = 0; i < b->count; ++i) {
@@ -1178,6 +1214,23 @@ int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
         else if (r.status != FCM_OK && worst == FCM_OK) worst = r.status;
     }
     return worst;
+}
+
+int fcm_batch_timeline(fcm_batch* b, int32_t inst, double* us, int32_t cap, int32_t* count) {
+    if (!b || inst < 0 || inst >= b->count || (cap > 0 && !us) || cap < 0) return FCM_EINVAL;
+    if (!b->solved) return FCM_ESTATE;
+    const BatchInst& in = b->h_inst[inst];
+    const int32_t nphase = b->h_recs[inst].passes + 1;
+    if (count) *count = nphase;
+    const int32_t m = std::min(cap, nphase);
+    if (m <= 0) return FCM_OK;
+    std::vector<uint64_t> ticks((size_t)m);
+    const double* base = b->d_hist + in.hist + (int64_t)(in.max_iter + 2) * (in.C + 2);
+    FCM_HIP(hipMemcpyAsync(ticks.data(), base, sizeof(uint64_t) * m, hipMemcpyDeviceToHost, b->stream));
+    FCM_HIP(hipStreamSynchronize(b->stream));
+    const uint64_t t0 = b->h_sync->t_start;
+    for (int32_t q = 0; q < m; ++q) us[q] = (double)(int64_t)(ticks[(size_t)q] - t0) / b->clock_mhz;
+    return FCM_OK;
 }
 
 int fcm_batch_solve_warm(fcm_batch* b, fcm_mlp* net, int32_t check, fcm_result* out, fcm_result* plain,
@@ -1234,7 +1287,7 @@ int fcm_batch_labels(fcm_batch* b, uint8_t* d_labels) {
     a.tiles = b->d_tiles;
     a.recs = b->d_recs;
     a.hist = b->d_hist;
-    a.ntiles = (int32_t)b->h_tiles.size();
+    a.ntiles = (int32_t)b->coarse_tiles;  // the coarse set covers every voxel once
     a.bytewise = (((uintptr_t)b->d_x ^ (uintptr_t)d_labels) & 15) ? 1 : 0;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.ntiles, 4LL * b->ncu));
     hipError_t e = launch_batch_labels(a, grid, b->stream);

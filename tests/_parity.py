@@ -3,8 +3,9 @@
 Tolerances follow the arithmetic of the GPU path: FP32 memberships (a few
 ulp, ~3e-7), FP32 centroids fed to the pass (relative 6e-8), Kahan-compensated
 FP32 partial sums and an FP64 (or compensated FP32) cross-block reduction.
-  * centroids: |v_gpu,j^t - v_j^t| <= max(1e-5 * max(|v_j^t|, 1), E_j^t).
-    1e-5 relative is the required bound.  E^t is the forward error that an
+  * centroids: |v_gpu,j^t - v_j^t| <= max(1e-5 * max(|v_j^t|, 1), E_j^t);
+    at the returned iterate of a converged solve 1e-5 * max(|v_j^T|, 1) with
+    no widening.  1e-5 relative is the required bound.  E^t is the forward error that an
     iteration committing 2^-22 relative per step (a few FP32 ulp: the
     rounding of v^t fed to the pass, the FP32 memberships and partial sums)
     reaches along the oracle's own trajectory, E^t = |dF/dv| E^(t-1) +
@@ -19,10 +20,12 @@ FP32 partial sums and an FP64 (or compensated FP32) cross-block reduction.
     sees (at least the FP32 rounding of v^t): a centroid error e changes each
     q = (x - v)^2 by about 2 sqrt(q) e, which dominates when voxels sit on
     their centroids and J is tiny
-  * change:    |delta_gpu - delta_ora| <= 2e-6 + 0.2 * delta_ora
-                 + S(v^t) e^t + S(v^(t-1)) e^(t-1)
-    delta is a difference of memberships; the first two terms cover the FP32
-    rounding of the memberships themselves.  The last two propagate the
+  * change:    |delta_gpu - delta_ora| <= 2e-6 + S(v^t) e^t + S(v^(t-1)) e^(t-1)
+    delta is a difference of two memberships in [0, 1], each computed in
+    FP32 with a relative error of a few ulp, so the rounding of the
+    memberships themselves moves it by at most a few 1e-7; 2e-6 is 2^-23
+    times 16.8 (the largest excess over the propagated terms measured over
+    the GPU suite is 1.3e-7).  The last two terms propagate the
     centroid difference to first order: the pass evaluates Eq.4 at
     fl32(v_gpu^t), which differs from the oracle's v^t by
     e^t = max_j |fl32(v_gpu,j^t) - v_j^t| (at least the FP32 rounding of v^t,
@@ -50,7 +53,7 @@ from oracle import fcm_hist
 
 V_TOL = 1e-5
 J_TOL = 1e-5
-D_ABS, D_REL = 2e-6, 0.20
+D_ABS, D_REL = 2e-6, 0.0
 STEP_REL = 2.0 ** -22   # relative error allowed per FP32 iteration (a few ulp)
 MARGIN = 5e-3
 # FCM_PARITY_LOG=<path>: append one JSON line per compared iteration (the
@@ -209,8 +212,9 @@ def compare(res, gtraj, otraj, eps, report=None, n=None, hist=None, m=2.0):
         dvg = np.abs(np.asarray(vs[t]) - vo)
         ev = float(np.max(dvg / np.maximum(np.abs(vo), 1.0)))
         vt = bd.v_tol(t)
-        if t < T and not np.all(dvg <= vt):
-            # intermediate iterates only: the returned v^T always meets 1e-5
+        if (t < T or getattr(res, "status", 0) != 0) and not np.all(dvg <= vt):
+            # intermediate iterates, and the last iterate of a solve that ran
+            # out of iterations; a converged v^T always meets 1e-5
             vt = bd.v_tol(t, widen=True)
         assert np.all(dvg <= vt), (f"centroids at t={t}: rel err {ev:.3e} (bound {np.max(vt / np.maximum(np.abs(vo), 1.0)):.3e})"
                                    f"\n gpu {vs[t]}\n ora {vo}")

@@ -168,6 +168,11 @@ def test_learned_start_validation(lib):
     assert lib.fcm_batch_targets(FAKE, 1, FAKE) == L.FCM_EINVAL
     assert lib.fcm_batch_targets(FAKE, 9, FAKE) == L.FCM_EINVAL
     assert lib.fcm_set_wait_limit(None, 1.0, None) == L.FCM_EINVAL
+    assert lib.fcm_batch_timeline(None, 0, None, 0, None) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_tail_tiling(None, 48, 1) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_tail_tiling(FAKE, -1, 1) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_tail_tiling(FAKE, 48, 0) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_tail_tiling(FAKE, 48, 65) == L.FCM_EINVAL
 
 
 def test_autotune_validation(lib):

@@ -153,3 +153,30 @@ def test_batch_512_instances(torch_dev):
     for (x, p), r, tr in zip(items, res, trajs):
         check_instance(x, p, r, tr, lab[start:start + x.size])
         start += x.size
+
+
+def test_batch_timeline_and_repeat_across_tilings(torch_dev):
+    """fcm_batch_timeline: one commit time per phase, increasing; and the
+    same tiling gives the same bits in a second launch, after solves under
+    another tiling (the instances progress at their own pace, but each
+    reduces its rows in tile order)."""
+    torch, dev = torch_dev
+    from paper_1601_00072_amd import FCMBatch
+    items = mixed_instances(20, 13)
+    announce("batch timeline")
+    flat = np.concatenate([x for x, _ in items])
+    x = torch.from_numpy(flat).to(dev)
+    with FCMBatch(x, [a.size for a, _ in items], [p for _, p in items]) as b:
+        b.set_tiling(chunks_per_thread=1, grid=0)
+        first = b.solve()
+        for i, r in enumerate(first):
+            us = b.timeline(i)
+            assert us.shape == (r.passes + 1,)
+            assert np.all(np.diff(us) > 0.0) and us[0] >= 0.0
+        b.set_tiling(chunks_per_thread=8, grid=0)
+        b.solve()
+        b.set_tiling(chunks_per_thread=1, grid=0)
+        again = b.solve()
+    for a, c in zip(first, again):
+        assert a.iters == c.iters and a.status == c.status and a.J == c.J
+        assert np.array_equal(a.centroids, c.centroids)

@@ -437,7 +437,9 @@ def test_batch_warm_falls_back_per_instance(torch_dev):
     from paper_1601_00072_amd import FCMBatch
     announce("batch warm fall-back")
     tri = three_level_image()
-    two = np.concatenate([np.full(1500, 30, np.uint8), np.full(1500, 200, np.uint8)])
+    # two noisy levels: both starts reach the same minimum (J > 0)
+    rng = np.random.default_rng(5)
+    two = np.clip(np.rint(np.concatenate([rng.normal(30, 6, 1500), rng.normal(200, 6, 1500)])), 0, 255).astype(np.uint8)
     xs = [two, tri, two]
     flat = torch.from_numpy(np.concatenate(xs)).to(d)
     h_tri = fcm_hist.histogram(tri)
@@ -453,8 +455,9 @@ def test_batch_warm_falls_back_per_instance(torch_dev):
             assert np.allclose(warm[1].centroids, plain.v[plain.T], rtol=1e-5)
             off = two.size
             assert np.array_equal(lab[off:off + tri.size], fcm_hist.level_labels(plain.v[plain.T])[tri])
-            for i in (0, 2):   # two levels: both starts end on the levels themselves
-                assert np.allclose(warm[i].centroids, [30.0, 200.0], rtol=1e-6)
+            for i in (0, 2):   # the same minimum from either start
+                assert np.allclose(warm[i].centroids, pl[i].centroids, rtol=1e-5)
+                assert abs(warm[i].J - pl[i].J) <= 1e-6 * pl[i].J
             w2, u2, p2 = b.solve_warm(net, check=False)
             assert p2 is None and list(u2) == [True, True, True]
             assert w2[1].iters == worse.T and np.allclose(w2[1].centroids, worse.v[worse.T], rtol=1e-5)

@@ -26,8 +26,9 @@ def announce(*what):
 
 
 class _Res:
-    def __init__(self, iters):
+    def __init__(self, iters, status=0):
         self.iters = iters
+        self.status = status
 
 
 def check(torch_dev, x, C, m, eps, init, max_iter=300):

@@ -59,6 +59,7 @@ def run_gpu(torch_dev, x_np, C, m, eps, seed, driver, offset=0, max_iter=300, st
 @dataclasses.dataclass
 class _Res:
     iters: int
+    status: int = 0
 
 
 def shifted(tr):
@@ -81,9 +82,9 @@ def check(x, C, m, eps, seed, res, traj, lab, max_iter=300):
         ora = fcm_ref.solve_random_u(x, C, m, 0.0, max(res.iters, T_ora) + 1, r)
     osh = shifted(ora)
     if res.iters != T_ora:
-        P.check_iterations(_Res(res.iters - 1), T_ora - 1, osh, eps, hist=hist, m=m, gpu_vs=vs[1:])
+        P.check_iterations(_Res(res.iters - 1, res.status), T_ora - 1, osh, eps, hist=hist, m=m, gpu_vs=vs[1:])
     gsh = (vs[1:], [float("nan")] + list(ds[2:]), Js[1:])
-    err = P.compare(_Res(res.iters - 1), gsh, osh, eps, hist=hist, m=m)
+    err = P.compare(_Res(res.iters - 1, res.status), gsh, osh, eps, hist=hist, m=m)
     # delta^1 against the random U^0: the FP32 draw normalisation is within the
     # fixed terms; the centroid difference at v^1 propagates as for any pass
     bd = P.Bounds(hist, m, osh, vs[1:])
