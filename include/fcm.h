@@ -408,6 +408,17 @@ int fcm_mlp_load(fcm_mlp* net, const char* path);
  * Allocates and frees temporaries; waits for the stream. */
 int fcm_histogram(const uint8_t* d_x, const int64_t* offsets, int32_t count, float* d_hist, void* stream);
 
+/* fcm_histogram for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and wait, but its workspace (the instance offsets and the
+ * counters) lives in a fixed array of about 1 MiB in the library's device
+ * memory, one per device for the life of the process, so the call allocates
+ * nothing.  At most 1,024 instances per call: FCM_EINVAL beyond that (see
+ * fcm_last_error).  The counters are cleared by a kernel at every call.  Calls
+ * on one device share the array, so two calls that overlap in time on one
+ * device (other threads, other streams) race: serialise them. */
+int fcm_histogram_noalloc(const uint8_t* d_x, const int64_t* offsets, int32_t count, float* d_hist, void* stream);
+
 /* Start centroids from histograms: BF16 inference, then v = 255 y sorted
  * ascending, clamped to the instance's grey-level range [lo, hi] (read off
  * its histogram), consecutive gaps of at least 1.  d_v0[count][C] doubles

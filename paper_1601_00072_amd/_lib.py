@@ -51,7 +51,7 @@ EXPORTS = (
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
     "fcm_confusion", "fcm_dice", "fcm_paper_solve", "fcm_solve_async", "fcm_solve_wait",
     "fcm_mlp_save", "fcm_mlp_load", "fcm_batch_solve_warm", "fcm_batch_targets", "fcm_set_wait_limit",
-    "fcm_batch_timeline", "fcm_batch_set_tail_tiling",
+    "fcm_batch_timeline", "fcm_batch_set_tail_tiling", "fcm_histogram_noalloc",
 )
 
 
@@ -205,6 +205,8 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_targets.restype = ctypes.c_int
     lib.fcm_histogram.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
     lib.fcm_histogram.restype = ctypes.c_int
+    lib.fcm_histogram_noalloc.argtypes = [vp, ctypes.POINTER(i64), i32, vp, vp]
+    lib.fcm_histogram_noalloc.restype = ctypes.c_int
     lib.fcm_paper_solve.argtypes = [vp, i64, ctypes.POINTER(FcmParams), vp, ctypes.POINTER(FcmResult), vp, vp, vp,
                                     ctypes.POINTER(FcmPaperStats)]
     lib.fcm_paper_solve.restype = ctypes.c_int

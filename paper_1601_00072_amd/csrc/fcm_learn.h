@@ -27,6 +27,9 @@ const uint16_t* mlp_bf16_weights(fcm_mlp* net, hipStream_t s, int* rc);
 int histogram_copies(int count);
 hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
                             float* hist, hipStream_t s);
+// the same on counters that are already zero (no memset)
+hipError_t launch_histogram_counts(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n,
+                                   uint32_t* counts, float* hist, hipStream_t s);
 hipError_t launch_gemm(bool ta, bool tb, const float* A, const float* B, float* Cm, int M, int N, int K,
                        const float* bias, int relu, const float* mask, hipStream_t s);
 hipError_t launch_colsum(const float* G, int M, int N, float* out, hipStream_t s);

@@ -11,6 +11,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
+#include "fcm.h"
+#include "fcm_host.h"
 #include "fcm_internal.h"
 #include "fcm_learn.h"
 #include "fcm_learn_dev.h"
@@ -75,11 +79,11 @@ __global__ __launch_bounds__(kBlock) void hist_norm_kernel(uint32_t* counts, con
 
 int histogram_copies(int count) { return count == 1 ? kHistCopies : 1; }
 
-hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
-                            float* hist, hipStream_t s) {
+// counting and normalisation on counters that are already zero
+hipError_t launch_histogram_counts(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n,
+                                   uint32_t* counts, float* hist, hipStream_t s) {
     const int copies = histogram_copies(count);
-    hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * 256 * (size_t)count * copies, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     const int64_t chunks = (max_n + 15) / 16;
     const int64_t cap = count == 1 ? 1024 : 64;  // a single instance may use the whole device
     int64_t gx64 = (chunks + kBlock * 16 - 1) / (kBlock * 16);
@@ -94,6 +98,14 @@ hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int coun
     }
     hipLaunchKernelGGL(hist_norm_kernel, dim3(count), dim3(256), 0, s, counts, d_offsets, hist, copies);
     return hipGetLastError();
+}
+
+hipError_t launch_histogram(const uint8_t* x, const int64_t* d_offsets, int count, int64_t max_n, uint32_t* counts,
+                            float* hist, hipStream_t s) {
+    const int copies = histogram_copies(count);
+    hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * 256 * (size_t)count * copies, s);
+    if (e != hipSuccess) return e;
+    return launch_histogram_counts(x, d_offsets, count, max_n, counts, hist, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,4 +325,79 @@ hipError_t launch_warm_post(const float* Y, const float* hist, int count, int C,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// histograms without allocation (fcm_histogram_noalloc)
+// ---------------------------------------------------------------------------
+
+// The workspace of fcm_histogram in a fixed device array: the instance
+// offsets, then the counters ([count][copies][256]; one instance uses
+// kHistCopies copies, more instances one copy each).  Each device holds its
+// own copy of the array for the life of the process.
+constexpr int kNoAllocMaxCount = 1024;
+constexpr size_t kNoAllocOffBytes = (sizeof(int64_t) * (kNoAllocMaxCount + 1) + 255) / 256 * 256;
+constexpr size_t kNoAllocCountWords = 256 * (size_t)kNoAllocMaxCount;
+static_assert((size_t)kHistCopies <= (size_t)kNoAllocMaxCount, "one instance's copies fit");
+static __device__ __align__(256) unsigned char scratch[kNoAllocOffBytes + sizeof(uint32_t) * kNoAllocCountWords];
+
+__global__ __launch_bounds__(kBlock) void zero_words_kernel(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0u;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (in host code the array's
+// name is not a device address); looked up once per device.
+int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_err(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return FCM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return dev_err(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FCM_OK;
+}
+
+}  // namespace
+
 }  // namespace fcm
+
+extern "C" int fcm_histogram_noalloc(const uint8_t* d_x, const int64_t* offsets, int32_t count, float* d_hist,
+                                     void* stream) {
+    using namespace fcm;
+    if (!d_x || !offsets || !d_hist || count < 1 || offsets[0] != 0) return FCM_EINVAL;
+    int64_t max_n = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (offsets[i + 1] <= offsets[i]) return FCM_EINVAL;
+        max_n = offsets[i + 1] - offsets[i] > max_n ? offsets[i + 1] - offsets[i] : max_n;
+    }
+    if (max_n > (int64_t)UINT32_MAX) return FCM_EINVAL;
+    if (count > kNoAllocMaxCount) {
+        last_error() = "fcm_histogram_noalloc: more instances than its fixed workspace holds (1024)";
+        return FCM_EINVAL;
+    }
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc != FCM_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t* d_off = reinterpret_cast<int64_t*>(base);
+    uint32_t* d_counts = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(base) + kNoAllocOffBytes);
+    const int64_t words = 256 * (int64_t)count * histogram_copies(count);
+    FCM_HIP(hipMemcpyAsync(d_off, offsets, sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice, s));
+    // the array keeps the previous call's counts: clear them (a kernel, no memset node)
+    const int zgrid = (int)((words + kBlock - 1) / kBlock < 1024 ? (words + kBlock - 1) / kBlock : 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zgrid), dim3(kBlock), 0, s, d_counts, words);
+    FCM_HIP(hipGetLastError());
+    FCM_HIP(launch_histogram_counts(d_x, d_off, count, max_n, d_counts, d_hist, s));
+    FCM_HIP(hipStreamSynchronize(s));
+    return FCM_OK;
+}

@@ -149,6 +149,11 @@ def test_learned_start_validation(lib):
     off = (ctypes.c_int64 * 2)(1, 10)      # does not start at 0
     assert lib.fcm_histogram(FAKE, off, 1, FAKE, None) == L.FCM_EINVAL
     assert lib.fcm_histogram(None, off, 1, FAKE, None) == L.FCM_EINVAL
+    assert lib.fcm_histogram_noalloc(None, off, 1, FAKE, None) == L.FCM_EINVAL
+    off2 = (ctypes.c_int64 * 3)(0, 10, 10)
+    assert lib.fcm_histogram_noalloc(FAKE, off2, 2, FAKE, None) == L.FCM_EINVAL
+    big = (ctypes.c_int64 * 1026)(*range(1026))
+    assert lib.fcm_histogram_noalloc(FAKE, big, 1025, FAKE, None) == L.FCM_EINVAL
     assert lib.fcm_warm_centroids(None, FAKE, 1, FAKE, None) == L.FCM_EINVAL
     r = L.FcmResult()
     assert lib.fcm_solve_warm(None, None, 0, ctypes.byref(r), None, None) == L.FCM_EINVAL
