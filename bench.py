@@ -290,7 +290,7 @@ def recorded_counters(shape, C, m, tuning):
         return None
     out = {}
     for k, v in kv.items():
-        if k in ("valu_counters", "sources_digest", "tuning", "workload"):
+        if k in ("valu_counters", "sources_digest", "tuning", "workload") or "=" in k:
             continue
         try:
             out[k] = float(v)
