@@ -517,6 +517,7 @@ def batched(dev, tune_cache):
             res = b.solve()
         torch.cuda.synchronize()
         el_b = (time.perf_counter() - t0) / reps
+        tl = [b.timeline(i) for i in range(len(xs))]
     vox_passes = sum(a.size * r.passes for a, r in zip(xs, res))
     # algorithmic work of every instance at its own C and pass count: the
     # fixed count's roofline time, and the library's own lane-op count
@@ -547,7 +548,31 @@ def batched(dev, tune_cache):
             "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b,
             "roofline_frac_wall": t_roof / el_b,
             "roofline_frac_wall_library_count": ops / el_b / PEAK_LANE_OPS,
-            "tiling": {"chunks_per_thread": cpt, "grid": bgrid}}
+            "tiling": {"chunks_per_thread": cpt, "grid": bgrid},
+            "timeline": batch_timeline(tl, [a.size for a in xs], t_roof)}
+
+
+def batch_timeline(tl, sizes, t_roof):
+    """What the per-instance commit times of the last batched solve show:
+    instances still running and the share of all voxel-passes committed at
+    fractions of the launch, and the instance that finished last (its pass
+    count and mean pass time).  The roofline line is where a launch that
+    kept every lane busy would have committed all the work."""
+    import numpy as np
+    end = max(float(t[-1]) for t in tl)
+    total = sum(s * (len(t) - 1) for s, t in zip(sizes, tl))
+    marks = (0.1, 0.25, 0.5, 0.75, 0.9)
+    running, done = {}, {}
+    for f in marks:
+        at = f * end
+        running[f"{round(f * 100)}%"] = int(sum(1 for t in tl if t[-1] > at))
+        done[f"{round(f * 100)}%"] = float(sum(s * np.count_nonzero(t[1:] <= at) for s, t in zip(sizes, tl)) / total)
+    last = max(range(len(tl)), key=lambda i: tl[i][-1])
+    t = tl[last]
+    return {"launch_us": end, "roofline_us": t_roof * 1e6, "instances_running": running,
+            "voxel_passes_committed": done,
+            "last_instance": {"voxels": int(sizes[last]), "passes": len(t) - 1,
+                              "us_per_pass_mean": float((t[-1] - t[0]) / max(1, len(t) - 1))}}
 
 
 # ---- learned warm start (training set, held-out slices and volumes) ----------

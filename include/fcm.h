@@ -254,9 +254,9 @@ int fcm_batch_init(fcm_batch** b, const uint8_t* d_x, const int64_t* offsets, in
  * rounding only). */
 int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid);
 
-/* Tiles of the later passes: from pass from_pass on (>= 0; default 48) every
+/* Tiles of the later passes: from pass from_pass on (>= 0; default 96) every
  * instance runs on a second, finer tile set of chunks_per_thread chunks per
- * thread (1..64; default 2).  Few instances remain by then, and each pass of
+ * thread (1..64; default 4).  Few instances remain by then, and each pass of
  * the longest solves lies on the launch's critical path, so more, smaller
  * tiles let more blocks share it; the early passes keep the coarse tiles and
  * their lower per-tile cost.  The switch depends on the pass index only, so

@@ -286,7 +286,7 @@ class FCMBatch:
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_set_tiling")
 
-    def set_tail_tiling(self, from_pass: int = 48, chunks_per_thread: int = 2):
+    def set_tail_tiling(self, from_pass: int = 96, chunks_per_thread: int = 4):
         """Finer tiles from pass `from_pass` on (fcm_batch_set_tail_tiling)."""
         rc = self._lib.fcm_batch_set_tail_tiling(self._h, int(from_pass), int(chunks_per_thread))
         if rc != L.FCM_OK:

@@ -145,8 +145,8 @@ constexpr int kBatchDecF64 = 2 * kMaxC + 1;  // offset of the FP64 halves
 constexpr uint64_t kBatchClaim = 1ull;
 constexpr uint64_t kBatchArrive = 1ull << 16;
 constexpr uint32_t kBatchDoneClaims = 0x8000u;
-constexpr int32_t kBatchFineFrom = 48;      // default first pass on the fine tiles
-constexpr int32_t kBatchFineChunks = 2;     // default chunks per thread of a fine tile
+constexpr int32_t kBatchFineFrom = 96;      // default first pass on the fine tiles
+constexpr int32_t kBatchFineChunks = 4;     // default chunks per thread of a fine tile
 constexpr int32_t kBatchChunks = 8;         // default chunks per thread of a coarse tile
 constexpr int32_t kBatchMaxTiles = 0x6000;  // tiles per instance: a phase's claims stay below 2^16 (every
                                             // arrival also claims, so at most twice the tiles plus one
@@ -160,7 +160,7 @@ struct BatchInst {
     int32_t C, mclass, max_iter, kahan_only;
     int32_t given;       // start mode (0 spaced, 1 v0, 2 dv0)
     int32_t tile0, ntiles;    // coarse tiles: phase 0 and passes below BatchArgs::fine_from
-    int32_t tile0f, ntilesf;  // fine tiles (one chunk per thread): the later passes
+    int32_t tile0f, ntilesf;  // fine tiles: the passes from BatchArgs::fine_from on
     int32_t pad;
     float alpha, mexp;
     double eps;
