@@ -508,7 +508,7 @@ def batched(dev, tune_cache):
     flat = torch.from_numpy(np.concatenate(xs)).to(dev)
     n = flat.numel()
     with FCMBatch(flat, [a.size for a in xs], [dict(n_clusters=c, m=2.0, eps=1e-5) for c in Cs]) as b:
-        cpt, bgrid, _ = b.autotune(cache=tune_cache, reps=1)
+        bs, cpt, bgrid, _ = b.autotune(cache=tune_cache, reps=1)
         b.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -548,7 +548,7 @@ def batched(dev, tune_cache):
             "ms_per_instance_loop": el_l * 1e3, "speedup_vs_instance_loop": el_l / el_b,
             "roofline_frac_wall": t_roof / el_b,
             "roofline_frac_wall_library_count": ops / el_b / PEAK_LANE_OPS,
-            "tiling": {"chunks_per_thread": cpt, "grid": bgrid},
+            "tiling": {"block": bs, "chunks_per_thread": cpt, "grid": bgrid},
             "timeline": batch_timeline(tl, [a.size for a in xs], t_roof)}
 
 

@@ -246,17 +246,25 @@ int fcm_batch_init(fcm_batch** b, const uint8_t* d_x, const int64_t* offsets, in
                    const fcm_params* params, void* stream);
 
 /* Tile size: chunks_per_thread 16-voxel chunks per thread and tile (1..64,
- * default 8; a tile is 256 threads wide; an instance that would need more
- * than 24,576 tiles gets larger ones), and the launch grid (0 = as many blocks
- * as fit on the device).  Rebuilds the tile table.  The tiling fixes the
+ * default 4; a tile is one block wide, fcm_batch_set_block; an instance that
+ * would need more than 24,576 tiles gets larger ones), and the launch grid
+ * (0 = as many blocks as fit on the device).  Rebuilds the tile table.  The tiling fixes the
  * order in which an instance's partial sums are added, so results are
  * reproducible for a given tiling (and differ between tilings by FP32
  * rounding only). */
 int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid);
 
+/* Threads per block of the batched kernel: 512 (default; one block per CU,
+ * so a tile, and a whole single-tile phase, runs on a whole CU) or 256 (two
+ * blocks per CU).  A tile holds threads x chunks_per_thread chunks, so tile
+ * sizes scale with the block size.  Results are reproducible for a given
+ * block size and tiling.  Rebuilds the tile table; FCM_EINVAL for other
+ * sizes. */
+int fcm_batch_set_block(fcm_batch* b, int32_t threads);
+
 /* Tiles of the later passes: from pass from_pass on (>= 0; default 96) every
  * instance runs on a second, finer tile set of chunks_per_thread chunks per
- * thread (1..64; default 4).  Few instances remain by then, and each pass of
+ * thread (1..64; default 2).  Few instances remain by then, and each pass of
  * the longest solves lies on the launch's critical path, so more, smaller
  * tiles let more blocks share it; the early passes keep the coarse tiles and
  * their lower per-tile cost.  The switch depends on the pass index only, so
@@ -305,12 +313,13 @@ void fcm_batch_destroy(fcm_batch* b);
  * the chosen configuration's median solve time, may be NULL). */
 int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning* chosen, double* ms);
 
-/* Batch: tiles of 1, 2, 4, 8 or 16 chunks per thread, on the largest grid
- * the device holds and on half of it.  Key: instance count, largest C and
- * floor(log2 of the total voxels).  The chosen tiling is applied
- * (fcm_batch_set_tiling); outputs may be NULL. */
-int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* chunks_per_thread, int32_t* grid,
-                       double* ms);
+/* Batch: blocks of 512 and 256 threads x tiles of 1, 2, 4, 8 or 16 chunks
+ * per thread, on the largest grid the device holds and on half of it (the
+ * tail tiling stays as set).  Key: instance count, largest C and floor(log2
+ * of the total voxels).  The chosen block size and tiling are applied
+ * (fcm_batch_set_block, fcm_batch_set_tiling); outputs may be NULL. */
+int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* block,
+                       int32_t* chunks_per_thread, int32_t* grid, double* ms);
 
 /* ---- learned warm start -------------------------------------------------
  * A small network maps the normalised 256-bin grey-level histogram of an

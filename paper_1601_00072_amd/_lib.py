@@ -51,7 +51,7 @@ EXPORTS = (
     "fcm_warm_centroids", "fcm_solve_warm", "fcm_batch_set_start", "fcm_autotune", "fcm_batch_autotune",
     "fcm_confusion", "fcm_dice", "fcm_paper_solve", "fcm_solve_async", "fcm_solve_wait",
     "fcm_mlp_save", "fcm_mlp_load", "fcm_batch_solve_warm", "fcm_batch_targets", "fcm_set_wait_limit",
-    "fcm_batch_timeline", "fcm_batch_set_tail_tiling", "fcm_histogram_noalloc",
+    "fcm_batch_timeline", "fcm_batch_set_tail_tiling", "fcm_histogram_noalloc", "fcm_batch_set_block",
 )
 
 
@@ -164,6 +164,8 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_set_tiling.restype = ctypes.c_int
     lib.fcm_batch_set_tail_tiling.argtypes = [vp, i32, i32]
     lib.fcm_batch_set_tail_tiling.restype = ctypes.c_int
+    lib.fcm_batch_set_block.argtypes = [vp, i32]
+    lib.fcm_batch_set_block.restype = ctypes.c_int
     lib.fcm_batch_solve.argtypes = [vp, ctypes.POINTER(FcmResult)]
     lib.fcm_batch_solve.restype = ctypes.c_int
     lib.fcm_batch_labels.argtypes = [vp, vp]
@@ -227,7 +229,8 @@ def load() -> ctypes.CDLL:
     lib.fcm_batch_set_start.restype = ctypes.c_int
     lib.fcm_autotune.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(FcmTuning), f64p]
     lib.fcm_autotune.restype = ctypes.c_int
-    lib.fcm_batch_autotune.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), f64p]
+    lib.fcm_batch_autotune.argtypes = [vp, ctypes.c_char_p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32), f64p]
     lib.fcm_batch_autotune.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -281,12 +281,18 @@ class FCMBatch:
             self._h = None
             raise FcmError(rc, "fcm_batch_init")
 
-    def set_tiling(self, chunks_per_thread: int = 8, grid: int = 0):
+    def set_tiling(self, chunks_per_thread: int = 4, grid: int = 0):
         rc = self._lib.fcm_batch_set_tiling(self._h, int(chunks_per_thread), int(grid))
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_set_tiling")
 
-    def set_tail_tiling(self, from_pass: int = 96, chunks_per_thread: int = 4):
+    def set_block(self, threads: int = 512):
+        """Threads per block of the batched kernel, 256 or 512 (fcm_batch_set_block)."""
+        rc = self._lib.fcm_batch_set_block(self._h, int(threads))
+        if rc != L.FCM_OK:
+            raise FcmError(rc, "fcm_batch_set_block")
+
+    def set_tail_tiling(self, from_pass: int = 96, chunks_per_thread: int = 2):
         """Finer tiles from pass `from_pass` on (fcm_batch_set_tail_tiling)."""
         rc = self._lib.fcm_batch_set_tail_tiling(self._h, int(from_pass), int(chunks_per_thread))
         if rc != L.FCM_OK:
@@ -300,14 +306,14 @@ class FCMBatch:
         return [_result(r) for r in out]
 
     def autotune(self, cache: str | None = None, reps: int = 2):
-        """Pick the tile size and grid (see fcm_batch_autotune); returns
-        (chunks_per_thread, grid, median ms per batched solve)."""
-        cpt, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        """Pick the block size, tile size and grid (see fcm_batch_autotune);
+        returns (block, chunks_per_thread, grid, median ms per batched solve)."""
+        bs, cpt, grid, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         rc = self._lib.fcm_batch_autotune(self._h, None if cache is None else str(cache).encode(), int(reps),
-                                          ctypes.byref(cpt), ctypes.byref(grid), ctypes.byref(ms))
+                                          ctypes.byref(bs), ctypes.byref(cpt), ctypes.byref(grid), ctypes.byref(ms))
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_autotune")
-        return cpt.value, grid.value, ms.value
+        return bs.value, cpt.value, grid.value, ms.value
 
     def set_start(self, net: "MLP | None" = None, use=None):
         """Learned start for the instances whose C matches the network (and

@@ -155,7 +155,7 @@ __device__ __forceinline__ void publish_decision(uint64_t* dec, uint32_t round, 
 // Fused pass over one tile's voxels (thread-strided chunks, the next chunk
 // loaded while the current one is computed, plus the instance's ragged
 // voxels on its first tile).
-template <int C, int FORM, bool OLD>
+template <int C, int FORM, bool OLD, int BS>
 __device__ __forceinline__ void tile_body(const uint8_t* xi, const BatchInst& in, const BatchTile& tl,
                                           const float (&vn)[C], const float (&vo)[C], const Consts& kc, Acc<C>& acc) {
     const int tid = threadIdx.x;
@@ -164,7 +164,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* xi, const BatchInst& in
     int64_t c = tl.c0 + tid;
     uint4 cur = c < tl.c1 ? body[c] : z;
     while (c < tl.c1) {
-        const int64_t cn = c + kBlock;
+        const int64_t cn = c + BS;
         const uint4 nx = cn < tl.c1 ? body[cn] : z;
         chunk16<C, FORM, OLD>(cur, vn, vo, kc, acc);
         cur = nx;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* xi, const BatchInst& in
 
 // One tile of fused pass d.p; its partial row goes to the tagged row buffer,
 // or to LDS (`lrow`) when the phase has a single tile.
-template <int C>
+template <int C, int BS>
 __device__ __forceinline__ void tile_pass(const BatchArgs& a, int64_t t, const BatchInst& in, const BatchTile& tl,
                                           const Decision& d, uint32_t round, float* lrow) {
     float vn[C], vo[C];
@@ -202,37 +202,38 @@ __device__ __forceinline__ void tile_pass(const BatchArgs& a, int64_t t, const B
     const bool fast = separated<C>(vn) && (p == 0 || separated<C>(vo));
     if (fast && in.mclass == kM2) {
         if (p == 0)
-            tile_body<C, kProdM2, false>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kProdM2, false, BS>(xi, in, tl, vn, vo, kc, acc);
         else
-            tile_body<C, kProdM2, true>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kProdM2, true, BS>(xi, in, tl, vn, vo, kc, acc);
     } else if (fast) {
         if (p == 0)
-            tile_body<C, kProdPow, false>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kProdPow, false, BS>(xi, in, tl, vn, vo, kc, acc);
         else
-            tile_body<C, kProdPow, true>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kProdPow, true, BS>(xi, in, tl, vn, vo, kc, acc);
     } else {
         if (p == 0)
-            tile_body<C, kNormLog, false>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kNormLog, false, BS>(xi, in, tl, vn, vo, kc, acc);
         else
-            tile_body<C, kNormLog, true>(xi, in, tl, vn, vo, kc, acc);
+            tile_body<C, kNormLog, true, BS>(xi, in, tl, vn, vo, kc, acc);
     }
     if (lrow) {
-        write_partial_row<C>(acc, LocalRows<2 * C + 2>{lrow});
+        write_partial_row<C, BS>(acc, LocalRows<2 * C + 2>{lrow});
     } else {
         const BatchRows<2 * C + 2> rows{a.rows, round, a.sync, 0, 0, t};
-        write_partial_row<C>(acc, rows);
+        write_partial_row<C, BS>(acc, rows);
     }
 }
 
 // Phase 0 of one tile: the grey-level range of its voxels as two tagged
 // words (or in LDS, `lmm`, when the phase has a single tile).
+template <int BS>
 __device__ __forceinline__ void tile_range(const BatchArgs& a, int64_t t, const BatchInst& in, const BatchTile& tl,
                                            uint32_t round, uint32_t* lmm) {
     const int tid = threadIdx.x;
     const uint8_t* xi = a.x + in.base;
     uint32_t lo = 255u, hi = 0u;
     const uint4* body = reinterpret_cast<const uint4*>(xi + in.head);
-    for (int64_t c = tl.c0 + tid; c < tl.c1; c += kBlock) {
+    for (int64_t c = tl.c0 + tid; c < tl.c1; c += BS) {
         const uint4 w = body[c];
         const uint32_t words[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -254,7 +255,7 @@ __device__ __forceinline__ void tile_range(const BatchArgs& a, int64_t t, const 
             hi = max(hi, (uint32_t)xi[i]);
         }
     }
-    block_minmax(lo, hi);
+    block_minmax<BS>(lo, hi);
     if (tid == 0) {
         if (lmm) {
             lmm[0] = lo;
@@ -298,6 +299,7 @@ __device__ __forceinline__ void open_phase(const BatchArgs& a, int i, uint32_t r
 // the history, then pass 0 opens with this block on its tile 0 and the
 // decision in `d` (published for the other blocks when the pass has more
 // tiles).  Returns false (all threads) if a wait was abandoned.
+template <int BS>
 __device__ __forceinline__ bool finish_range(const BatchArgs& a, int i, const BatchInst& in, uint32_t round,
                                              const uint32_t* lmm, Decision& d) {
     uint32_t lo, hi;
@@ -315,7 +317,7 @@ __device__ __forceinline__ bool finish_range(const BatchArgs& a, int i, const Ba
             h = raw[1];
             return true;
         };
-        if (!reduce_minmax(get, in.ntiles, lo, hi)) return false;
+        if (!reduce_minmax<BS>(get, in.ntiles, lo, hi)) return false;
     }
     if (threadIdx.x == 0) {
         double* hv = a.hist + in.hist;
@@ -354,7 +356,7 @@ __device__ __forceinline__ bool finish_range(const BatchArgs& a, int i, const Ba
 // rule, record, then retire the instance or open pass p + 1 with this block
 // on its tile 0 and the decision in `d`.  Returns 0 (all threads) if a wait
 // was abandoned, 1 if the instance finished, 2 if pass p + 1 was opened.
-template <int C>
+template <int C, int BS>
 __device__ __forceinline__ int finish_pass(const BatchArgs& a, int i, const BatchInst& in, int p, uint32_t round,
                                            const float* lrow, Decision& d) {
     __shared__ Reduced<C> s_r;
@@ -362,11 +364,11 @@ __device__ __forceinline__ int finish_pass(const BatchArgs& a, int i, const Batc
     __shared__ double s_vcur[C];
     const bool fine = tile_set(a, round - a.round0 - 1u) != 0;
     if (lrow) {
-        if (!reduce_rows<C>(LocalRows<2 * C + 2>{const_cast<float*>(lrow)}, 1, in.kahan_only, s_r)) return 0;
+        if (!reduce_rows<C, BS>(LocalRows<2 * C + 2>{const_cast<float*>(lrow)}, 1, in.kahan_only, s_r)) return 0;
     } else {
         const BatchRows<2 * C + 2> rows{a.rows + (int64_t)(fine ? in.tile0f : in.tile0) * kBatchRowWords, round,
                                         a.sync, (uint64_t)wall_clock64(), a.spin_ticks, 0};
-        if (!reduce_rows<C>(rows, fine ? in.ntilesf : in.ntiles, in.kahan_only, s_r)) return 0;
+        if (!reduce_rows<C, BS>(rows, fine ? in.ntilesf : in.ntiles, in.kahan_only, s_r)) return 0;
     }
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -427,15 +429,17 @@ __device__ __forceinline__ int finish_pass(const BatchArgs& a, int i, const Batc
 }
 
 // Block-wide choice of an instance with tiles left: every thread inspects the
-// instances at rotation positions tid, tid + kBlock, ... from `start`; the
+// instances at rotation positions tid, tid + BS, ... from `start`; the
 // nearest in rotation order wins.  Blocks start their rotations at spread
 // positions, so that free blocks seldom race for the same tile.  Returns the
 // instance or -1 (all threads).
+template <int BS>
 __device__ __forceinline__ int pick_instance(const BatchArgs& a, int start) {
-    __shared__ int s_pos[kWaves];
+    constexpr int NW = BS / 64;
+    __shared__ int s_pos[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int best = 0x7FFFFFFF;
-    for (int j = tid; j < a.I; j += kBlock) {
+    for (int j = tid; j < a.I; j += BS) {
         int i = start + j;
         if (i >= a.I) i -= a.I;
         const uint64_t w = __hip_atomic_load(a.ctl + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -450,7 +454,7 @@ __device__ __forceinline__ int pick_instance(const BatchArgs& a, int start) {
     if (lane == 0) s_pos[wid] = best;
     __syncthreads();
     best = s_pos[0];
-    for (int w = 1; w < kWaves; ++w) best = min(best, s_pos[w]);
+    for (int w = 1; w < NW; ++w) best = min(best, s_pos[w]);
     __syncthreads();
     if (best == 0x7FFFFFFF) return -1;
     const int i = start + best;
@@ -459,7 +463,9 @@ __device__ __forceinline__ int pick_instance(const BatchArgs& a, int start) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock, 2) void fcm_batch_kernel(BatchArgs a) {
+// BS threads per block, two waves per SIMD (512 / BS blocks per CU)
+template <int BS>
+__global__ __launch_bounds__(BS, 512 / BS) void fcm_batch_kernel(BatchArgs a) {
     const int tid = threadIdx.x;
     BatchSync* sy = a.sync;
     __shared__ Decision s_d;
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(kBlock, 2) void fcm_batch_kernel(BatchArgs a) {
             const int go = s_go, sticky = s_inst;
             __syncthreads();
             if (!go) break;
-            const int i = sticky >= 0 ? sticky : (sticky == -3 ? -1 : pick_instance(a, start));
+            const int i = sticky >= 0 ? sticky : (sticky == -3 ? -1 : pick_instance<BS>(a, start));
             if (tid == 0) {
                 s_inst = -1;
                 if (i >= 0) {
@@ -576,17 +582,17 @@ __global__ __launch_bounds__(kBlock, 2) void fcm_batch_kernel(BatchArgs a) {
         const int64_t t = (int64_t)(fine ? in.tile0f : in.tile0) + k;
         const BatchTile tl = a.tiles[t];
         if (phase == 0u) {
-            tile_range(a, t, in, tl, tag, local ? s_mm : nullptr);
+            tile_range<BS>(a, t, in, tl, tag, local ? s_mm : nullptr);
         } else {
             float* lrow = local ? s_row : nullptr;
             switch (in.C) {
-                case 2: tile_pass<2>(a, t, in, tl, s_d, tag, lrow); break;
-                case 3: tile_pass<3>(a, t, in, tl, s_d, tag, lrow); break;
-                case 4: tile_pass<4>(a, t, in, tl, s_d, tag, lrow); break;
-                case 5: tile_pass<5>(a, t, in, tl, s_d, tag, lrow); break;
-                case 6: tile_pass<6>(a, t, in, tl, s_d, tag, lrow); break;
-                case 7: tile_pass<7>(a, t, in, tl, s_d, tag, lrow); break;
-                default: tile_pass<8>(a, t, in, tl, s_d, tag, lrow); break;
+                case 2: tile_pass<2, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                case 3: tile_pass<3, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                case 4: tile_pass<4, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                case 5: tile_pass<5, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                case 6: tile_pass<6, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                case 7: tile_pass<7, BS>(a, t, in, tl, s_d, tag, lrow); break;
+                default: tile_pass<8, BS>(a, t, in, tl, s_d, tag, lrow); break;
             }
         }
         __syncthreads();  // the row is written (issued) before the arrival
@@ -613,18 +619,18 @@ __global__ __launch_bounds__(kBlock, 2) void fcm_batch_kernel(BatchArgs a) {
         if (last) {
             int r;
             if (phase == 0u) {
-                r = finish_range(a, inst, in, tag, local ? s_mm : nullptr, s_d) ? 2 : 0;
+                r = finish_range<BS>(a, inst, in, tag, local ? s_mm : nullptr, s_d) ? 2 : 0;
             } else {
                 const int p = (int)phase - 1;
                 const float* lrow = local ? s_row : nullptr;
                 switch (in.C) {
-                    case 2: r = finish_pass<2>(a, inst, in, p, tag, lrow, s_d); break;
-                    case 3: r = finish_pass<3>(a, inst, in, p, tag, lrow, s_d); break;
-                    case 4: r = finish_pass<4>(a, inst, in, p, tag, lrow, s_d); break;
-                    case 5: r = finish_pass<5>(a, inst, in, p, tag, lrow, s_d); break;
-                    case 6: r = finish_pass<6>(a, inst, in, p, tag, lrow, s_d); break;
-                    case 7: r = finish_pass<7>(a, inst, in, p, tag, lrow, s_d); break;
-                    default: r = finish_pass<8>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 2: r = finish_pass<2, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 3: r = finish_pass<3, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 4: r = finish_pass<4, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 5: r = finish_pass<5, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 6: r = finish_pass<6, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    case 7: r = finish_pass<7, BS>(a, inst, in, p, tag, lrow, s_d); break;
+                    default: r = finish_pass<8, BS>(a, inst, in, p, tag, lrow, s_d); break;
                 }
             }
             if (r == 0) break;
@@ -721,17 +727,21 @@ hipError_t launch_batch_targets(const BatchRec* recs, int32_t I, int32_t C, floa
     return hipGetLastError();
 }
 
-hipError_t batch_max_grid(int ncu, int* max_grid) {
+hipError_t batch_max_grid(int block, int ncu, int* max_grid) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(fcm_batch_kernel), kBlock, 0);
+    const void* k = block == 512 ? reinterpret_cast<const void*>(fcm_batch_kernel<512>)
+                                 : reinterpret_cast<const void*>(fcm_batch_kernel<256>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block == 512 ? 512 : 256, 0);
     if (e != hipSuccess) return e;
     *max_grid = per_cu * ncu;
     return hipSuccess;
 }
 
-hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(fcm_batch_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_batch(const BatchArgs& a, int block, int grid, hipStream_t s) {
+    if (block == 512)
+        hipLaunchKernelGGL(fcm_batch_kernel<512>, dim3(grid), dim3(512), 0, s, a);
+    else
+        hipLaunchKernelGGL(fcm_batch_kernel<256>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

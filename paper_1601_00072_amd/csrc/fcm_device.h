@@ -677,10 +677,11 @@ __device__ __forceinline__ void run_pass(const PassArgs& a, int p, const float (
 // Block reduction of the thread sums into this block's partial row: wave
 // butterflies, then the waves in order (Kahan).  Row entries: for each k < C
 // num (sum, comp), den (sum, comp); then J (sum, comp); then max |dU|.
-template <int C, typename Rows>
+template <int C, int BS = kBlock, typename Rows>
 __device__ __forceinline__ void write_partial_row(const Acc<C>& acc, const Rows& rows) {
     constexpr int NQ = 2 * C + 1;
-    __shared__ float s_red[kWaves][NQ + 1];
+    constexpr int NW = BS / 64;
+    __shared__ float s_red[NW][NQ + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     float f[NQ];
 #pragma unroll
@@ -699,11 +700,11 @@ __device__ __forceinline__ void write_partial_row(const Acc<C>& acc, const Rows&
     __syncthreads();
     if (tid < NQ) {
         float s = 0.f, c = 0.f;
-        for (int w = 0; w < kWaves; ++w) kahan_add(s, c, s_red[w][tid]);
+        for (int w = 0; w < NW; ++w) kahan_add(s, c, s_red[w][tid]);
         rows.put_pair(tid, s, c);
     } else if (tid == NQ) {
         float mm = s_red[0][NQ];
-        for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_red[w][NQ]);
+        for (int w = 1; w < NW; ++w) mm = fmaxf(mm, s_red[w][NQ]);
         rows.put_max(NQ, mm);
     }
 }
@@ -718,13 +719,14 @@ struct Reduced {
 // rows t, t + blockDim, ...; then wave butterflies and the waves in order); the
 // result is written to `out` (shared) and valid in every thread after the
 // call.  Returns false in every thread if a row could not be obtained.
-template <int C, typename Rows>
+template <int C, int BS = kBlock, typename Rows>
 __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>& out) {
     constexpr int NQ = 2 * C + 1;
     constexpr int R = partial_rows(C);
-    __shared__ double s_sum[kWaves][NQ];
-    __shared__ float s_lo[kWaves][NQ];
-    __shared__ float s_max[kWaves];
+    constexpr int NW = BS / 64;
+    __shared__ double s_sum[NW][NQ];
+    __shared__ float s_lo[NW][NQ];
+    __shared__ float s_max[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     float dm = 0.f;
     int bad = 0;
@@ -735,7 +737,7 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
         acc[q] = 0.0;
         hi[q] = lo[q] = 0.f;
     }
-    for (int b = tid; b < G; b += kBlock) {
+    for (int b = tid; b < G; b += BS) {
         float v[R];
         if (!rows.template get<R>(b, v)) {
             bad = 1;
@@ -781,10 +783,10 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
         double r;
         if (!kahan_only) {
             r = s_sum[0][tid];
-            for (int w = 1; w < kWaves; ++w) r += s_sum[w][tid];
+            for (int w = 1; w < NW; ++w) r += s_sum[w][tid];
         } else {
             float h = (float)s_sum[0][tid], l = s_lo[0][tid];
-            for (int w = 1; w < kWaves; ++w) {
+            for (int w = 1; w < NW; ++w) {
                 float s, e;
                 two_sum(h, (float)s_sum[w][tid], s, e);
                 h = s;
@@ -795,7 +797,7 @@ __device__ bool reduce_rows(const Rows& rows, int G, int kahan_only, Reduced<C>&
         out.res[tid] = r;
     } else if (tid == NQ) {
         float mm = s_max[0];
-        for (int w = 1; w < kWaves; ++w) mm = fmaxf(mm, s_max[w]);
+        for (int w = 1; w < NW; ++w) mm = fmaxf(mm, s_max[w]);
         out.dm = mm;
     }
     __syncthreads();
@@ -1022,8 +1024,10 @@ __device__ __forceinline__ void thread_minmax(const uint8_t* x, int64_t n, int64
 }
 
 // block min/max; (lo, hi) is valid in thread 0 after the call
+template <int BS = kBlock>
 __device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi) {
-    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    constexpr int NW = BS / 64;
+    __shared__ uint32_t s_lo[NW], s_hi[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     lo = wave_min_u32(lo);
     hi = wave_max_u32(hi);
@@ -1033,7 +1037,7 @@ __device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi) {
     }
     __syncthreads();
     if (tid == 0) {
-        for (int w = 1; w < kWaves; ++w) {
+        for (int w = 1; w < NW; ++w) {
             lo = min(lo, s_lo[w]);
             hi = max(hi, s_hi[w]);
         }
@@ -1043,14 +1047,15 @@ __device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi) {
 // Whole-block reduction of the G (lo, hi) rows obtained through
 // get(b, lo_b, hi_b); valid in every thread after the call.  Returns false in
 // every thread if a row could not be obtained.
-template <typename Get>
+template <int BS = kBlock, typename Get>
 __device__ __forceinline__ bool reduce_minmax(const Get& get, int G, uint32_t& lo, uint32_t& hi) {
-    __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+    constexpr int NW = BS / 64;
+    __shared__ uint32_t s_lo[NW], s_hi[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     lo = 255u;
     hi = 0u;
     int bad = 0;
-    for (int b = tid; b < G; b += kBlock) {
+    for (int b = tid; b < G; b += BS) {
         uint32_t l, h;
         if (!get(b, l, h)) {
             bad = 1;
@@ -1069,7 +1074,7 @@ __device__ __forceinline__ bool reduce_minmax(const Get& get, int G, uint32_t& l
     __syncthreads();
     lo = s_lo[0];
     hi = s_hi[0];
-    for (int w = 1; w < kWaves; ++w) {
+    for (int w = 1; w < NW; ++w) {
         lo = min(lo, s_lo[w]);
         hi = max(hi, s_hi[w]);
     }

@@ -19,7 +19,7 @@ struct HandleShape {
 };
 struct BatchShape {
     int64_t voxels;     // all instances
-    int count, max_C, device, max_grid, chunks_per_thread, grid;
+    int count, max_C, device, max_grid, chunks_per_thread, grid, block;
 };
 int handle_shape(const fcm_handle* h, HandleShape* s);
 int batch_shape(const fcm_batch* b, BatchShape* s);

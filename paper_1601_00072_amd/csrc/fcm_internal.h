@@ -146,8 +146,9 @@ constexpr uint64_t kBatchClaim = 1ull;
 constexpr uint64_t kBatchArrive = 1ull << 16;
 constexpr uint32_t kBatchDoneClaims = 0x8000u;
 constexpr int32_t kBatchFineFrom = 96;      // default first pass on the fine tiles
-constexpr int32_t kBatchFineChunks = 4;     // default chunks per thread of a fine tile
-constexpr int32_t kBatchChunks = 8;         // default chunks per thread of a coarse tile
+constexpr int32_t kBatchFineChunks = 2;     // default chunks per thread of a fine tile
+constexpr int32_t kBatchChunks = 4;         // default chunks per thread of a coarse tile
+constexpr int32_t kBatchBlock = 512;        // default threads per block of the batched kernel
 constexpr int32_t kBatchMaxTiles = 0x6000;  // tiles per instance: a phase's claims stay below 2^16 (every
                                             // arrival also claims, so at most twice the tiles plus one
                                             // per concurrent claimer, kMaxPersistGrid)
@@ -216,8 +217,9 @@ struct BatchLabelArgs {
     int32_t ntiles, bytewise;
 };
 
-hipError_t batch_max_grid(int ncu, int* max_grid);
-hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
+// the batched kernel is built for 256- and 512-thread blocks
+hipError_t batch_max_grid(int block, int ncu, int* max_grid);
+hipError_t launch_batch(const BatchArgs& a, int block, int grid, hipStream_t s);
 hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_targets(const BatchRec* recs, int32_t I, int32_t C, float* out, hipStream_t s);
 

@@ -885,6 +885,7 @@ struct fcm_batch {
     std::vector<const double*> own_dv0;  // FCM_INIT_DEVICE start arrays of the caller
     hipStream_t stream = nullptr;
     int device = 0, ncu = 256, max_grid = 1, grid = 1, grid_req = 0;
+    int block = kBatchBlock;       // threads per block of the batched kernel (256 or 512)
     int chunks_per_thread = kBatchChunks;
     int fine_from = kBatchFineFrom;   // passes from this one on use the fine tiles
     int fine_chunks = kBatchFineChunks;  // chunks per thread of a fine tile
@@ -958,7 +959,7 @@ int batch_build_tiles(fcm_batch* b) {
         for (int32_t i = 0; i < b->count; ++i) {
             BatchInst& in = b->h_inst[i];
             const int64_t tile_chunks =
-                std::max<int64_t>((int64_t)kBlock * cpt, (in.nbody + kBatchMaxTiles - 1) / kBatchMaxTiles);
+                std::max<int64_t>((int64_t)b->block * cpt, (in.nbody + kBatchMaxTiles - 1) / kBatchMaxTiles);
             const int32_t first = (int32_t)b->h_tiles.size();
             int64_t c0 = 0;
             do {
@@ -1066,7 +1067,7 @@ int fcm_batch_init(fcm_batch** out, const uint8_t* d_x, const int64_t* offsets, 
         clock_khz = 100000;
     b->clock_mhz = clock_khz / 1000.0;
     b->spin_ticks = (uint64_t)(kBarrierLimitSeconds * 1000.0 * clock_khz);
-    if ((e = batch_max_grid(b->ncu, &b->max_grid)) != hipSuccess) return fail(dev_err(e, "occupancy"));
+    if ((e = batch_max_grid(b->block, b->ncu, &b->max_grid)) != hipSuccess) return fail(dev_err(e, "occupancy"));
     b->max_grid = std::max(1, std::min(b->max_grid, kMaxPersistGrid));
 
     if (hipMalloc(&b->d_inst, sizeof(BatchInst) * count) != hipSuccess) return fail(FCM_ENOMEM);
@@ -1094,6 +1095,17 @@ int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid) 
         return FCM_EINVAL;
     b->chunks_per_thread = chunks_per_thread;
     b->grid_req = grid;
+    b->solved = false;
+    return batch_build_tiles(b);
+}
+
+int fcm_batch_set_block(fcm_batch* b, int32_t threads) {
+    if (!b || (threads != 256 && threads != 512)) return FCM_EINVAL;
+    int max_grid = 0;
+    hipError_t e = batch_max_grid(threads, b->ncu, &max_grid);
+    if (e != hipSuccess) return dev_err(e, "occupancy");
+    b->block = threads;
+    b->max_grid = std::max(1, std::min(max_grid, kMaxPersistGrid));
     b->solved = false;
     return batch_build_tiles(b);
 }
@@ -1183,7 +1195,7 @@ int fcm_batch_solve(fcm_batch* b, fcm_result* out) {
     a.fine_from = b->fine_from;
     a.round0 = round0;
     a.spin_ticks = b->spin_ticks;
-    hipError_t e = launch_batch(a, b->grid, b->stream);
+    hipError_t e = launch_batch(a, b->block, b->grid, b->stream);
     if (e != hipSuccess) return dev_err(e, "launch (batch)");
     FCM_HIP(hipMemcpyAsync(b->h_recs, b->d_recs, sizeof(BatchRec) * b->count, hipMemcpyDeviceToHost, b->stream));
     FCM_HIP(hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, b->stream));
@@ -1349,6 +1361,7 @@ int batch_shape(const fcm_batch* b, BatchShape* s) {
     s->max_grid = b->max_grid;
     s->chunks_per_thread = b->chunks_per_thread;
     s->grid = b->grid_req;
+    s->block = b->block;
     return FCM_OK;
 }
 

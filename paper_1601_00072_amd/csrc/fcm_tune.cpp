@@ -35,7 +35,7 @@ namespace {
 constexpr int kMaxAllGatherGrid = 512;  // larger all-gather grids flood the fabric with polls
 
 struct Choice {
-    int32_t v[7];   // single: driver grid unroll exchange launch graph_k; batch: chunks_per_thread grid
+    int32_t v[7];   // single: driver grid unroll exchange launch graph_k; batch: block chunks_per_thread grid
     double ms;
 };
 
@@ -259,53 +259,70 @@ int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning
     return fcm_reset(h);
 }
 
-int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* chunks_per_thread,
-                       int32_t* grid, double* ms) {
+int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* block,
+                       int32_t* chunks_per_thread, int32_t* grid, double* ms) {
     if (!b || reps < 1 || reps > 100) return FCM_EINVAL;
     BatchShape s{};
     int rc = batch_shape(b, &s);
     if (rc != FCM_OK) return rc;
     std::ostringstream key;
-    key << "batch " << device_tag(s.device) << " count=" << s.count << " maxC=" << s.max_C
+    key << "batch2 " << device_tag(s.device) << " count=" << s.count << " maxC=" << s.max_C
         << " vlog2=" << log2_floor(s.voxels);
+    auto apply = [&](int bs, int cpt, int g) {
+        int r = bs == s.block ? FCM_OK : fcm_batch_set_block(b, bs);
+        if (r == FCM_OK) r = fcm_batch_set_tiling(b, cpt, g);
+        if (r == FCM_OK) s.block = bs;
+        return r;
+    };
+    auto report = [&](int bs, int cpt, int g, double t_ms) {
+        if (block) *block = bs;
+        if (chunks_per_thread) *chunks_per_thread = cpt;
+        if (grid) *grid = g;
+        if (ms) *ms = t_ms;
+    };
     Choice c{};
-    if (load_choice(cache_path, key.str(), 2, &c) && fcm_batch_set_tiling(b, c.v[0], c.v[1]) == FCM_OK) {
-        if (chunks_per_thread) *chunks_per_thread = c.v[0];
-        if (grid) *grid = c.v[1];
-        if (ms) *ms = c.ms;
+    if (load_choice(cache_path, key.str(), 3, &c) && apply(c.v[0], c.v[1], c.v[2]) == FCM_OK) {
+        report(c.v[0], c.v[1], c.v[2], c.ms);
         return FCM_OK;
     }
     std::vector<fcm_result> ref((size_t)s.count), r((size_t)s.count);
     rc = fcm_batch_solve(b, ref.data());
     if (rc < 0 && rc != FCM_ENUMERIC) return rc;
-    int best_cpt = s.chunks_per_thread, best_grid = s.grid;
+    const int e_bs = s.block, e_cpt = s.chunks_per_thread, e_grid = s.grid;
+    int best_bs = e_bs, best_cpt = e_cpt, best_grid = e_grid;
     double best_ms = time_batch(b, reps, r);
     if (best_ms < 0) return FCM_EDEVICE;
-    for (int cpt : {1, 2, 4, 8, 16}) {
-        for (int g : {0, std::max(1, s.max_grid / 2)}) {
-            if (cpt == s.chunks_per_thread && g == s.grid) continue;
-            if (fcm_batch_set_tiling(b, cpt, g) != FCM_OK) continue;
-            rc = fcm_batch_solve(b, r.data());
-            if (rc < 0 && rc != FCM_ENUMERIC) continue;
-            bool ok = true;
-            for (int i = 0; i < s.count && ok; ++i) ok = agrees(r[(size_t)i], ref[(size_t)i]);
-            if (!ok) continue;
-            const double t_ms = time_batch(b, reps, r);
-            if (t_ms >= 0 && t_ms < best_ms) {
-                best_ms = t_ms;
-                best_cpt = cpt;
-                best_grid = g;
+    for (int bs : {512, 256}) {
+        for (int cpt : {1, 2, 4, 8, 16}) {
+            for (int half : {0, 1}) {
+                if (apply(bs, cpt, 0) != FCM_OK) continue;
+                BatchShape cur{};
+                if (batch_shape(b, &cur) != FCM_OK) continue;
+                const int g = half ? std::max(1, cur.max_grid / 2) : 0;
+                if (bs == e_bs && cpt == e_cpt && g == e_grid) continue;  // timed above
+                if (g && fcm_batch_set_tiling(b, cpt, g) != FCM_OK) continue;
+                rc = fcm_batch_solve(b, r.data());
+                if (rc < 0 && rc != FCM_ENUMERIC) continue;
+                bool ok = true;
+                for (int i = 0; i < s.count && ok; ++i) ok = agrees(r[(size_t)i], ref[(size_t)i]);
+                if (!ok) continue;
+                const double t_ms = time_batch(b, reps, r);
+                if (t_ms >= 0 && t_ms < best_ms) {
+                    best_ms = t_ms;
+                    best_bs = bs;
+                    best_cpt = cpt;
+                    best_grid = g;
+                }
             }
         }
     }
-    if ((rc = fcm_batch_set_tiling(b, best_cpt, best_grid)) != FCM_OK) return rc;
-    c.v[0] = best_cpt;
-    c.v[1] = best_grid;
+    if ((rc = apply(best_bs, best_cpt, best_grid)) != FCM_OK) return rc;
+    c.v[0] = best_bs;
+    c.v[1] = best_cpt;
+    c.v[2] = best_grid;
     c.ms = best_ms;
-    store_choice(cache_path, key.str(), 2, c);
-    if (chunks_per_thread) *chunks_per_thread = best_cpt;
-    if (grid) *grid = best_grid;
-    if (ms) *ms = best_ms;
+    store_choice(cache_path, key.str(), 3, c);
+    report(best_bs, best_cpt, best_grid, best_ms);
     return FCM_OK;
 }
 

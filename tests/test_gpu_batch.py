@@ -55,6 +55,9 @@ def run_batch(torch_dev, items, offset=0, tiling=None):
     x = buf[offset:offset + flat.size]
     with FCMBatch(x, [a.size for a, _ in items], [p for _, p in items]) as b:
         if tiling:
+            tiling = dict(tiling)
+            if "block" in tiling:
+                b.set_block(tiling.pop("block"))
             b.set_tiling(**tiling)
         res = b.solve()
         trajs = [[b.trajectory(i, t) for t in range(r.iters + 1)] for i, r in enumerate(res)]
@@ -101,11 +104,12 @@ def test_batch_mixed_against_oracle(torch_dev, seed, offset):
         start += x.size
 
 
-@pytest.mark.parametrize("cpt,grid", [(1, 0), (2, 7), (16, 0), (4, 1)])
-def test_batch_tiling(torch_dev, cpt, grid):
+@pytest.mark.parametrize("block,cpt,grid", [(512, 1, 0), (512, 2, 7), (512, 16, 0), (512, 4, 1), (256, 1, 0),
+                                            (256, 8, 0), (256, 2, 3)])
+def test_batch_tiling(torch_dev, block, cpt, grid):
     items = mixed_instances(12, 7)
-    announce("batch tiling cpt", cpt, "grid", grid)
-    res, trajs, lab = run_batch(torch_dev, items, tiling=dict(chunks_per_thread=cpt, grid=grid))
+    announce("batch tiling block", block, "cpt", cpt, "grid", grid)
+    res, trajs, lab = run_batch(torch_dev, items, tiling=dict(block=block, chunks_per_thread=cpt, grid=grid))
     start = 0
     for (x, p), r, tr in zip(items, res, trajs):
         check_instance(x, p, r, tr, lab[start:start + x.size])
@@ -175,6 +179,9 @@ def test_batch_timeline_and_repeat_across_tilings(torch_dev):
             assert np.all(np.diff(us) > 0.0) and us[0] >= 0.0
         b.set_tiling(chunks_per_thread=8, grid=0)
         b.solve()
+        b.set_block(256)
+        b.solve()
+        b.set_block(512)
         b.set_tiling(chunks_per_thread=1, grid=0)
         again = b.solve()
     for a, c in zip(first, again):

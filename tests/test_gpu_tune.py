@@ -70,9 +70,9 @@ def test_batch_autotune_keeps_parity(torch_dev, tmp_path):
     flat = torch.from_numpy(np.concatenate([x for x, _ in items])).to(d)
     cache = tmp_path / "tune.txt"
     with FCMBatch(flat, [x.size for x, _ in items], [p for _, p in items]) as b:
-        cpt, grid, ms = b.autotune(cache=cache, reps=2)
-        print("chosen tiling", cpt, grid, f"{ms:.3f} ms")
-        assert cpt in (1, 2, 4, 8, 16) and ms > 0
+        bs, cpt, grid, ms = b.autotune(cache=cache, reps=2)
+        print("chosen block and tiling", bs, cpt, grid, f"{ms:.3f} ms")
+        assert bs in (256, 512) and cpt in (1, 2, 4, 8, 16) and ms > 0
         res = b.solve()
         trajs = [[b.trajectory(i, t) for t in range(r.iters + 1)] for i, r in enumerate(res)]
         lab = b.labels().cpu().numpy()
@@ -81,4 +81,4 @@ def test_batch_autotune_keeps_parity(torch_dev, tmp_path):
         check_instance(x, p, r, tr, lab[start:start + x.size])
         start += x.size
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("fcm-tune1\tbatch ")
+    assert len(lines) == 1 and lines[0].startswith("fcm-tune1\tbatch2 ")
