@@ -255,8 +255,8 @@ int fcm_batch_init(fcm_batch** b, const uint8_t* d_x, const int64_t* offsets, in
 int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid);
 
 /* Threads per block of the batched kernel: 512 (default; one block per CU,
- * so a tile, and a whole single-tile phase, runs on a whole CU) or 256 (two
- * blocks per CU).  A tile holds threads x chunks_per_thread chunks, so tile
+ * so a tile, and a whole single-tile phase, runs on a whole CU), 256 (two
+ * blocks per CU) or 128 (four).  A tile holds threads x chunks_per_thread chunks, so tile
  * sizes scale with the block size.  Results are reproducible for a given
  * block size and tiling.  Rebuilds the tile table; FCM_EINVAL for other
  * sizes. */
@@ -313,7 +313,7 @@ void fcm_batch_destroy(fcm_batch* b);
  * the chosen configuration's median solve time, may be NULL). */
 int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning* chosen, double* ms);
 
-/* Batch: blocks of 512 and 256 threads x tiles of 1, 2, 4, 8 or 16 chunks
+/* Batch: blocks of 512, 256 and 128 threads x tiles of 1, 2, 4, 8 or 16 chunks
  * per thread, on the largest grid the device holds and on half of it (the
  * tail tiling stays as set).  Key: instance count, largest C and floor(log2
  * of the total voxels).  The chosen block size and tiling are applied

@@ -287,7 +287,7 @@ class FCMBatch:
             raise FcmError(rc, "fcm_batch_set_tiling")
 
     def set_block(self, threads: int = 512):
-        """Threads per block of the batched kernel, 256 or 512 (fcm_batch_set_block)."""
+        """Threads per block of the batched kernel: 128, 256 or 512 (fcm_batch_set_block)."""
         rc = self._lib.fcm_batch_set_block(self._h, int(threads))
         if rc != L.FCM_OK:
             raise FcmError(rc, "fcm_batch_set_block")

@@ -463,9 +463,10 @@ __device__ __forceinline__ int pick_instance(const BatchArgs& a, int start) {
 
 }  // namespace
 
-// BS threads per block, two waves per SIMD (512 / BS blocks per CU)
+// BS threads per block; registers for two waves per SIMD (the second bound
+// counts waves per SIMD), so 512 / BS blocks share a CU
 template <int BS>
-__global__ __launch_bounds__(BS, 512 / BS) void fcm_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(BS, 2) void fcm_batch_kernel(BatchArgs a) {
     const int tid = threadIdx.x;
     BatchSync* sy = a.sync;
     __shared__ Decision s_d;
@@ -729,9 +730,10 @@ hipError_t launch_batch_targets(const BatchRec* recs, int32_t I, int32_t C, floa
 
 hipError_t batch_max_grid(int block, int ncu, int* max_grid) {
     int per_cu = 0;
-    const void* k = block == 512 ? reinterpret_cast<const void*>(fcm_batch_kernel<512>)
-                                 : reinterpret_cast<const void*>(fcm_batch_kernel<256>);
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block == 512 ? 512 : 256, 0);
+    const void* k = block == 512   ? reinterpret_cast<const void*>(fcm_batch_kernel<512>)
+                    : block == 128 ? reinterpret_cast<const void*>(fcm_batch_kernel<128>)
+                                   : reinterpret_cast<const void*>(fcm_batch_kernel<256>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0);
     if (e != hipSuccess) return e;
     *max_grid = per_cu * ncu;
     return hipSuccess;
@@ -740,6 +742,8 @@ hipError_t batch_max_grid(int block, int ncu, int* max_grid) {
 hipError_t launch_batch(const BatchArgs& a, int block, int grid, hipStream_t s) {
     if (block == 512)
         hipLaunchKernelGGL(fcm_batch_kernel<512>, dim3(grid), dim3(512), 0, s, a);
+    else if (block == 128)
+        hipLaunchKernelGGL(fcm_batch_kernel<128>, dim3(grid), dim3(128), 0, s, a);
     else
         hipLaunchKernelGGL(fcm_batch_kernel<256>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();

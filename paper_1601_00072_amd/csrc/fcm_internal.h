@@ -217,7 +217,7 @@ struct BatchLabelArgs {
     int32_t ntiles, bytewise;
 };
 
-// the batched kernel is built for 256- and 512-thread blocks
+// the batched kernel is built for 128-, 256- and 512-thread blocks
 hipError_t batch_max_grid(int block, int ncu, int* max_grid);
 hipError_t launch_batch(const BatchArgs& a, int block, int grid, hipStream_t s);
 hipError_t launch_batch_labels(const BatchLabelArgs& a, int grid, hipStream_t s);

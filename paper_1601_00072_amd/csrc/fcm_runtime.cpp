@@ -885,7 +885,7 @@ struct fcm_batch {
     std::vector<const double*> own_dv0;  // FCM_INIT_DEVICE start arrays of the caller
     hipStream_t stream = nullptr;
     int device = 0, ncu = 256, max_grid = 1, grid = 1, grid_req = 0;
-    int block = kBatchBlock;       // threads per block of the batched kernel (256 or 512)
+    int block = kBatchBlock;       // threads per block of the batched kernel (128, 256 or 512)
     int chunks_per_thread = kBatchChunks;
     int fine_from = kBatchFineFrom;   // passes from this one on use the fine tiles
     int fine_chunks = kBatchFineChunks;  // chunks per thread of a fine tile
@@ -1100,7 +1100,7 @@ int fcm_batch_set_tiling(fcm_batch* b, int32_t chunks_per_thread, int32_t grid) 
 }
 
 int fcm_batch_set_block(fcm_batch* b, int32_t threads) {
-    if (!b || (threads != 256 && threads != 512)) return FCM_EINVAL;
+    if (!b || (threads != 128 && threads != 256 && threads != 512)) return FCM_EINVAL;
     int max_grid = 0;
     hipError_t e = batch_max_grid(threads, b->ncu, &max_grid);
     if (e != hipSuccess) return dev_err(e, "occupancy");

@@ -186,6 +186,7 @@ def test_autotune_validation(lib):
     assert lib.fcm_autotune(None, None, 3, ctypes.byref(t), ctypes.byref(ms)) == L.FCM_EINVAL
     assert lib.fcm_batch_autotune(None, None, 2, None, None, None, None) == L.FCM_EINVAL
     assert lib.fcm_batch_set_block(None, 512) == L.FCM_EINVAL
+    assert lib.fcm_batch_set_block(FAKE, 64) == L.FCM_EINVAL
 
 
 def test_quality_validation(lib):

@@ -105,7 +105,7 @@ def test_batch_mixed_against_oracle(torch_dev, seed, offset):
 
 
 @pytest.mark.parametrize("block,cpt,grid", [(512, 1, 0), (512, 2, 7), (512, 16, 0), (512, 4, 1), (256, 1, 0),
-                                            (256, 8, 0), (256, 2, 3)])
+                                            (256, 8, 0), (256, 2, 3), (128, 2, 0), (128, 16, 5)])
 def test_batch_tiling(torch_dev, block, cpt, grid):
     items = mixed_instances(12, 7)
     announce("batch tiling block", block, "cpt", cpt, "grid", grid)
@@ -180,6 +180,8 @@ def test_batch_timeline_and_repeat_across_tilings(torch_dev):
         b.set_tiling(chunks_per_thread=8, grid=0)
         b.solve()
         b.set_block(256)
+        b.solve()
+        b.set_block(128)
         b.solve()
         b.set_block(512)
         b.set_tiling(chunks_per_thread=1, grid=0)
