@@ -268,10 +268,12 @@ int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32
     std::ostringstream key;
     key << "batch2 " << device_tag(s.device) << " count=" << s.count << " maxC=" << s.max_C
         << " vlog2=" << log2_floor(s.voxels);
+    // block size, then tiling; s follows the batch's state whatever fails
     auto apply = [&](int bs, int cpt, int g) {
         int r = bs == s.block ? FCM_OK : fcm_batch_set_block(b, bs);
         if (r == FCM_OK) r = fcm_batch_set_tiling(b, cpt, g);
-        if (r == FCM_OK) s.block = bs;
+        BatchShape now{};
+        if (batch_shape(b, &now) == FCM_OK) s = now;
         return r;
     };
     auto report = [&](int bs, int cpt, int g, double t_ms) {
