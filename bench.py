@@ -415,7 +415,7 @@ def histogram_domain(dev, cases):
 
 
 def paper_protocol(dev, x, shape):
-    """The paper's own protocol on the headline volume: random memberships U^0
+    """The paper's own protocol on the given volume (the 128x128x64 one): random memberships U^0
     (five seeds), centroids first, eps = 0.005; iterations, time to converge
     (labels included) and the final centroids, beside the evenly spaced
     start at the same eps."""
@@ -442,7 +442,7 @@ def paper_protocol(dev, x, shape):
 def paper_design(dev, x, shape, fused_ms, eps):
     """The paper's GPU structure (per-cluster kernels, Algorithm 2 reductions,
     U copied to the host every iteration for the stopping test) on the
-    headline volume, against the fused persistent solve of the same start."""
+    given volume (the 128x128x64 one), against the fused persistent solve of the same start."""
     import torch
 
     from paper_1601_00072_amd import paper_baseline
