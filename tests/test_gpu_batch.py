@@ -1,6 +1,8 @@
 """GPU parity of the batched solver: every instance of one persistent launch
 against the FP64 oracle at matched iterations, and against the single-instance
 path."""
+import os
+
 import numpy as np
 import pytest
 
@@ -146,13 +148,29 @@ def test_batch_repeat_and_determinism(torch_dev):
         assert np.array_equal(a.centroids, c.centroids)
 
 
-def test_batch_512_instances(torch_dev):
+def shipped_batch_tiling():
+    """block, chunks_per_thread and grid of the shipped choice for the batch."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_00072_amd",
+                        "tuning_mi355x.txt")
+    with open(path) as fh:
+        for line in fh:
+            f = line.rstrip("\n").split("\t")
+            if len(f) == 3 and f[1].startswith("batch2 ") and " count=512 " in f[1]:
+                v = [int(a) for a in f[2].split()[:3]]
+                return dict(block=v[0], chunks_per_thread=v[1], grid=v[2])
+    pytest.fail("no shipped batch choice")
+
+
+@pytest.mark.parametrize("which", ["default", "shipped"])
+def test_batch_512_instances(torch_dev, which):
     """The batched workload: 496 slices (side U{64..512}) and 16 cubes (side
-    U{96..160}), C_i in 3..8, m = 2, all in one launch."""
+    U{96..160}), C_i in 3..8, m = 2, all in one launch, with the default
+    tiling and with the shipped tuning the benchmark times."""
     inst = batch_instances()
     items = [(phantom(p).ravel(), dict(n_clusters=c, m=2.0, eps=1e-5, max_iter=300)) for p, c in inst]
-    announce("batch 512 instances", sum(x.size for x, _ in items), "voxels")
-    res, trajs, lab = run_batch(torch_dev, items)
+    tiling = None if which == "default" else shipped_batch_tiling()
+    announce("batch 512 instances", sum(x.size for x, _ in items), "voxels, tiling", tiling)
+    res, trajs, lab = run_batch(torch_dev, items, tiling=tiling)
     start = 0
     for (x, p), r, tr in zip(items, res, trajs):
         check_instance(x, p, r, tr, lab[start:start + x.size])
