@@ -313,11 +313,11 @@ void fcm_batch_destroy(fcm_batch* b);
  * the chosen configuration's median solve time, may be NULL). */
 int fcm_autotune(fcm_handle* h, const char* cache_path, int32_t reps, fcm_tuning* chosen, double* ms);
 
-/* Batch: blocks of 512, 256 and 128 threads x tiles of 1, 2, 4, 8 or 16 chunks
- * per thread, on the largest grid the device holds and on half of it (the
- * tail tiling stays as set).  Key: instance count, largest C and floor(log2
- * of the total voxels).  The chosen block size and tiling are applied
- * (fcm_batch_set_block, fcm_batch_set_tiling); outputs may be NULL. */
+/* Batch: blocks of 512, 256 and 128 threads x tiles of 1, 2, 3, 4, 5, 6, 8, 12
+ * or 16 chunks per thread, on the largest grid the device holds and on half
+ * of it (the tail tiling stays as set).  Key: instance count, largest C and
+ * floor(log2 of the total voxels).  The chosen block size and tiling are
+ * applied (fcm_batch_set_block, fcm_batch_set_tiling); outputs may be NULL. */
 int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32_t* block,
                        int32_t* chunks_per_thread, int32_t* grid, double* ms);
 

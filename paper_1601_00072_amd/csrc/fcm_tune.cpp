@@ -295,7 +295,7 @@ int fcm_batch_autotune(fcm_batch* b, const char* cache_path, int32_t reps, int32
     double best_ms = time_batch(b, reps, r);
     if (best_ms < 0) return FCM_EDEVICE;
     for (int bs : {512, 256, 128}) {
-        for (int cpt : {1, 2, 4, 8, 16}) {
+        for (int cpt : {1, 2, 3, 4, 5, 6, 8, 12, 16}) {
             for (int half : {0, 1}) {
                 if (apply(bs, cpt, 0) != FCM_OK) continue;
                 BatchShape cur{};
